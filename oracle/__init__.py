@@ -1,0 +1,190 @@
+"""FP64 CPU oracle of the tactile force field -- test infrastructure only.
+
+A plain, step-by-step evaluation of the penalty force field of Section III-C
+(SDF query at the tactile points, finite-difference normal, normal spring with
+depth-scaled damping, Coulomb-capped friction) written in C++ (FP64) and
+driven through ctypes.  It is used by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark, and by nothing else; it shares no code with
+the HIP library.  Every function is pinned in tests/test_oracle_*.py against
+closed forms, invariants, special cases and hand-derived worked examples.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tacsl_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(ctypes.Structure):
+    _fields_ = [("n_env", ctypes.c_int32), ("n_inst", ctypes.c_int32),
+                ("n_tmpl", ctypes.c_int32), ("n_sdf", ctypes.c_int32),
+                ("inst_env", ctypes.c_void_p), ("inst_tmpl", ctypes.c_void_p),
+                ("env_sdf", ctypes.c_void_p), ("tmpl_offset", ctypes.c_void_p),
+                ("tmpl_xyz", ctypes.c_void_p), ("sdf_dims", ctypes.c_void_p),
+                ("sdf_origin", ctypes.c_void_p), ("sdf_spacing", ctypes.c_void_p),
+                ("sdf_offset", ctypes.c_void_p), ("sdf_data", ctypes.c_void_p)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("pad_pose", ctypes.c_void_p), ("obj_pose", ctypes.c_void_p),
+                ("pad_twist", ctypes.c_void_p), ("obj_twist", ctypes.c_void_p),
+                ("params", ctypes.c_void_p), ("obj_pose_delta", ctypes.c_void_p)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_offsets.argtypes = [P, P]
+        lib.oracle_force_field.argtypes = [P, P, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
+        lib.oracle_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
+        lib.oracle_loss.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int]
+        lib.oracle_signature.argtypes = [P, P, P, ctypes.c_int]
+        lib.oracle_footprint.argtypes = [P, P, ctypes.c_int, P]
+        lib.oracle_footprint.restype = ctypes.c_int64
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _Bound:
+    """Keeps the numpy buffers alive while the C structs point at them."""
+
+    def __init__(self, scene, state):
+        self.keep = []
+
+        def c(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self.keep.append(a)
+            return a
+
+        self.sc = _Scene(
+            int(scene.n_env), int(scene.n_inst), int(scene.tmpl_offset.size - 1), int(scene.sdf_spacing.size),
+            _ptr(c(scene.inst_env, np.int32)), _ptr(c(scene.inst_tmpl, np.int32)),
+            _ptr(c(scene.env_sdf, np.int32)), _ptr(c(scene.tmpl_offset, np.int64)),
+            _ptr(c(scene.tmpl_xyz, np.float32)), _ptr(c(scene.sdf_dims, np.int32)),
+            _ptr(c(scene.sdf_origin, np.float32)), _ptr(c(scene.sdf_spacing, np.float32)),
+            _ptr(c(scene.sdf_offset, np.int64)), _ptr(c(scene.sdf_data, np.float32)))
+        delta = state.get("obj_pose_delta")
+        self.st = _State(
+            _ptr(c(state["pad_pose"], np.float64)), _ptr(c(state["obj_pose"], np.float64)),
+            _ptr(c(state["pad_twist"], np.float64)), _ptr(c(state["obj_twist"], np.float64)),
+            _ptr(c(state["params"], np.float64)),
+            None if delta is None else _ptr(c(delta, np.float64)))
+
+
+def offsets(scene):
+    b = _Bound(scene, _dummy_state(scene))
+    out = np.zeros(scene.n_inst + 1, dtype=np.int64)
+    _load().oracle_offsets(ctypes.byref(b.sc), _ptr(out))
+    return out
+
+
+def _dummy_state(scene):
+    return dict(pad_pose=np.zeros((scene.n_inst, 7)), obj_pose=np.zeros((scene.n_env, 7)),
+                pad_twist=np.zeros((scene.n_inst, 6)), obj_twist=np.zeros((scene.n_env, 6)),
+                params=np.zeros((scene.n_env, 4)))
+
+
+def force_field(scene, state, sel=None, nthreads=0, signature=False):
+    """Evaluate the selected instances (default: all).  Returns a dict of FP64 arrays.
+
+    ``state`` holds pad_pose, obj_pose, pad_twist, obj_twist, params and an
+    optional obj_pose_delta, each widened to FP64 (pass the FP32 inputs of the
+    GPU path to compare like with like).
+    """
+    if sel is None:
+        sel = np.arange(scene.n_inst, dtype=np.int32)
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    counts = np.diff(scene.tmpl_offset)[scene.inst_tmpl[sel]]
+    Ts = int(counts.sum())
+    b = _Bound(scene, state)
+    out = dict(depth=np.zeros(Ts), normal=np.zeros((3, Ts)), fn=np.zeros((3, Ts)),
+               ft=np.zeros((3, Ts)), wrench=np.zeros((sel.size, 6)))
+    sig = np.zeros((Ts, 4), dtype=np.int32) if signature else None
+    _load().oracle_force_field(ctypes.byref(b.sc), ctypes.byref(b.st), int(sel.size), _ptr(sel),
+                               _ptr(out["depth"]), _ptr(out["normal"]), _ptr(out["fn"]),
+                               _ptr(out["ft"]), _ptr(out["wrench"]), _ptr(sig), int(nthreads))
+    if signature:
+        out["sig"] = sig
+    return out
+
+
+def grad(scene, state, wa, wb, sel_env=None, mask=None, nthreads=0):
+    """Loss per selected env and its 16-direction gradient (dual numbers).
+
+    Columns: dt(3), dtheta(3), v_o(3), w_o(3), k_n, k_d, k_t, mu.
+    """
+    if sel_env is None:
+        sel_env = np.arange(scene.n_env, dtype=np.int32)
+    sel_env = np.ascontiguousarray(sel_env, dtype=np.int32)
+    b = _Bound(scene, state)
+    wa = np.ascontiguousarray(wa, dtype=np.float64)
+    wb = np.ascontiguousarray(wb, dtype=np.float64)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    loss = np.zeros(sel_env.size)
+    g = np.zeros((sel_env.size, 16))
+    _load().oracle_grad(ctypes.byref(b.sc), ctypes.byref(b.st), _ptr(wa), _ptr(wb), _ptr(m),
+                        int(sel_env.size), _ptr(sel_env), _ptr(loss), _ptr(g), int(nthreads))
+    return loss, g
+
+
+def loss(scene, state, wa, wb, sel_env=None, mask=None, nthreads=0):
+    if sel_env is None:
+        sel_env = np.arange(scene.n_env, dtype=np.int32)
+    sel_env = np.ascontiguousarray(sel_env, dtype=np.int32)
+    b = _Bound(scene, state)
+    wa = np.ascontiguousarray(wa, dtype=np.float64)
+    wb = np.ascontiguousarray(wb, dtype=np.float64)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    out = np.zeros(sel_env.size)
+    _load().oracle_loss(ctypes.byref(b.sc), ctypes.byref(b.st), _ptr(wa), _ptr(wb), _ptr(m),
+                        int(sel_env.size), _ptr(sel_env), _ptr(out), int(nthreads))
+    return out
+
+
+def signature(scene, state, nthreads=0):
+    b = _Bound(scene, state)
+    T = int(np.diff(scene.tmpl_offset)[scene.inst_tmpl].sum())
+    sig = np.zeros((T, 4), dtype=np.int32)
+    _load().oracle_signature(ctypes.byref(b.sc), ctypes.byref(b.st), _ptr(sig), int(nthreads))
+    return sig
+
+
+def footprint(scene, state, sel=None):
+    if sel is None:
+        sel = np.arange(scene.n_inst, dtype=np.int32)
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    b = _Bound(scene, state)
+    return int(_load().oracle_footprint(ctypes.byref(b.sc), ctypes.byref(b.st), int(sel.size), _ptr(sel)))
+
+
+def state64(scene, step=None, obj_pose_delta=None):
+    """The scene's FP32 state widened to FP64 (what the GPU path consumes)."""
+    st = {k: np.asarray(v, dtype=np.float64) for k, v in scene.state(step).items()}
+    if obj_pose_delta is not None:
+        st["obj_pose_delta"] = np.asarray(obj_pose_delta, dtype=np.float64)
+    return st

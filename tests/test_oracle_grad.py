@@ -1,0 +1,196 @@
+"""Pins of the oracle's forward-mode (dual-number) gradient.
+
+* Against FP64 central finite differences (h = 1e-6 in m, rad and m/s;
+  relative 1e-6 for the contact parameters) of the plain FP64 loss, with the
+  kink mask: a tactile point is dropped from the loss if its discrete
+  signature (cell, contact flag, stick/slip, |g| >= 1e-6) changes between the
+  base point and any perturbed evaluation.  The O(h^2) truncation term of the
+  central difference is ~2e-6 relative for the pose block at h = 1e-6 (it
+  quadruples at 2h), so the plain difference is held to 1e-5 and its
+  Richardson extrapolation (4 D(h) - D(2h)) / 3 to 1e-6.
+* Against closed-form partial derivatives of the force law of Section III-C:
+  d f_n / d k_n = delta n, d f_n / d k_d = d_dot phi n, d f_t / d mu = -|s| v_t/|v_t|
+  when slipping (0 when sticking), d f_t / d k_t = -v_t when sticking.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_06506_amd import workloads as wl
+from tests.scenes import rel_velocity_pad
+
+H = 1e-6
+
+
+def _perturbed_states(st, e_sel, H=H):
+    """16 +/- pairs of states, one per gradient direction (only envs in e_sel move)."""
+    out = []
+    E = st["obj_pose"].shape[0]
+    for d in range(16):
+        pair = []
+        for sgn in (+1, -1):
+            s = {k: v.copy() for k, v in st.items()}
+            if "obj_pose_delta" not in s:
+                s["obj_pose_delta"] = np.zeros((E, 6))
+            if d < 6:
+                s["obj_pose_delta"][e_sel, d] += sgn * H
+                step = H
+            elif d < 12:
+                s["obj_twist"][e_sel, d - 6] += sgn * H
+                step = H
+            else:
+                p = st["params"][e_sel, d - 12]
+                step_v = H * np.maximum(np.abs(p), 1.0)
+                s["params"][e_sel, d - 12] += sgn * step_v
+                step = step_v
+            pair.append(s)
+        out.append((pair, step))
+    return out
+
+
+def _fd_check(sc, st, n_check, seed):
+    """Dual gradient, central FD at h and 2h (same kink mask), and the mask."""
+    T = sc.n_taxels
+    wa, wb = wl.loss_weights(T, seed)
+    sel = np.arange(min(n_check, sc.n_env), dtype=np.int32)
+    perts = [_perturbed_states(st, sel, H), _perturbed_states(st, sel, 2 * H)]
+    sig0 = oracle.signature(sc, st)
+    keep = np.ones(T, dtype=bool)
+    for pert in perts:
+        for pair, _ in pert:
+            for s in pair:
+                keep &= np.all(oracle.signature(sc, s) == sig0, axis=1)
+    mask = keep.astype(np.uint8)
+    loss0, g = oracle.grad(sc, st, wa, wb, sel_env=sel, mask=mask)
+    fds = []
+    for pert in perts:
+        fd = np.zeros_like(g)
+        for d, (pair, step) in enumerate(pert):
+            lp = oracle.loss(sc, pair[0], wa, wb, sel_env=sel, mask=mask)
+            lm = oracle.loss(sc, pair[1], wa, wb, sel_env=sel, mask=mask)
+            fd[:, d] = (lp - lm) / (2 * step)
+        fds.append(fd)
+    np.testing.assert_allclose(loss0, oracle.loss(sc, st, wa, wb, sel_env=sel, mask=mask), rtol=1e-13)
+    return g, fds[0], fds[1], keep
+
+
+def _assert_blocks(g, fd, tol):
+    for blk in (slice(0, 6), slice(6, 12), slice(12, 16)):
+        num = np.linalg.norm(g[:, blk] - fd[:, blk], axis=1)
+        den = np.linalg.norm(g[:, blk], axis=1)
+        assert np.all(num <= tol * den + 1e-12), (blk, (num / den).max())
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_dual_gradient_matches_central_fd(seed):
+    sc = wl.make_small(cfg_id=40 + seed, n_env=6)
+    st = oracle.state64(sc)
+    g, fd1, fd2, keep = _fd_check(sc, st, 6, seed)
+    assert keep.mean() > 0.8
+    _assert_blocks(g, fd1, 1e-5)
+    _assert_blocks(g, (4 * fd1 - fd2) / 3, 1e-6)
+
+
+def test_dual_gradient_at_nonzero_pose_delta():
+    sc = wl.make_small(cfg_id=45, n_env=4)
+    rng = np.random.default_rng(3)
+    delta = np.concatenate([rng.uniform(-2e-4, 2e-4, (4, 3)), rng.uniform(-0.01, 0.01, (4, 3))], 1)
+    st = oracle.state64(sc, obj_pose_delta=delta)
+    g, fd1, fd2, keep = _fd_check(sc, st, 4, 7)
+    _assert_blocks(g, fd1, 1e-5)
+    _assert_blocks(g, (4 * fd1 - fd2) / 3, 1e-6)
+
+
+def test_parameter_partials_closed_form():
+    sc = wl.make_small(cfg_id=47, n_env=3)
+    st = oracle.state64(sc)
+    o = oracle.force_field(sc, st, signature=True)
+    T = sc.n_taxels
+    off = oracle.offsets(sc)
+    kn, kd, kt, mu = st["params"][0]
+    rng = np.random.default_rng(1)
+    contact = np.flatnonzero(o["depth"] > 0)
+    picks = rng.choice(contact, size=12, replace=False)
+    for j in picks:
+        i = int(np.searchsorted(off, j, side="right") - 1)
+        e = sc.inst_env[i]
+        xdot, _, _ = rel_velocity_pad(sc, st, i)
+        xd = xdot[j - off[i]]
+        n = o["normal"][:, j]
+        dep = o["depth"][j]
+        ddot = n @ xd
+        vt = xd - ddot * n
+        s = (kn - kd * ddot) * dep
+        for comp in range(3):
+            wa = np.zeros((3, T)); wb = np.zeros((3, T))
+            wa[comp, j] = 1.0
+            _, g = oracle.grad(sc, st, wa, wb, sel_env=np.array([e]))
+            np.testing.assert_allclose(g[0, 12], dep * n[comp], rtol=1e-9, atol=1e-15)
+            np.testing.assert_allclose(g[0, 13], -ddot * dep * n[comp], rtol=1e-9, atol=1e-15)
+            wa[:] = 0; wb[comp, j] = 1.0
+            _, g = oracle.grad(sc, st, wa, wb, sel_env=np.array([e]))
+            if o["sig"][j, 2] == 1:  # stick
+                np.testing.assert_allclose(g[0, 14], -vt[comp], rtol=1e-9, atol=1e-15)
+                assert g[0, 15] == 0.0
+            else:  # slip
+                vhat = vt / np.linalg.norm(vt)
+                np.testing.assert_allclose(g[0, 15], -abs(s) * vhat[comp], rtol=1e-9, atol=1e-15)
+                assert g[0, 14] == 0.0
+
+
+def test_velocity_gradient_is_minus_relative_velocity_gradient():
+    """Moving the object with +v is moving the pad with -v: gradients w.r.t.
+    the object's linear velocity and the relative velocity differ in sign."""
+    sc = wl.make_small(cfg_id=48, n_env=2, wmax=0.0, pad_wmax=0.0)
+    st = oracle.state64(sc)
+    wa, wb = wl.loss_weights(sc.n_taxels, 3)
+    _, g = oracle.grad(sc, st, wa, wb)
+    # shift the pads' velocity by +dv instead (world frame, both pads of env 0)
+    dv = 1e-6
+    fd = []
+    for a in range(3):
+        sp = {k: v.copy() for k, v in st.items()}
+        sm = {k: v.copy() for k, v in st.items()}
+        pads = np.flatnonzero(sc.inst_env == 0)
+        sp["pad_twist"][pads, a] += dv
+        sm["pad_twist"][pads, a] -= dv
+        fd.append((oracle.loss(sc, sp, wa, wb, sel_env=np.array([0]))
+                   - oracle.loss(sc, sm, wa, wb, sel_env=np.array([0])))[0] / (2 * dv))
+    np.testing.assert_allclose(-g[0, 6:9], fd, rtol=1e-5)
+
+
+def test_pose_gradient_convention_independent_of_exp():
+    """The pose columns are derivatives w.r.t. t_o <- t_o + dt and
+    R_o <- Exp(dtheta) R_o.  Perturb the object quaternion and translation
+    directly (numpy, without the oracle's own exponential map) and difference."""
+    sc = wl.make_small(cfg_id=49, n_env=3)
+    st = oracle.state64(sc)
+    wa, wb = wl.loss_weights(sc.n_taxels, 9)
+    sel = np.array([0, 1, 2], np.int32)
+    sig0 = oracle.signature(sc, st)
+    h = 1e-6
+    states = []
+    for d in range(6):
+        pair = []
+        for sgn in (+1, -1):
+            s = {k: v.copy() for k, v in st.items()}
+            if d < 3:
+                s["obj_pose"][:, 4 + d] += sgn * h
+            else:
+                ax = np.zeros(3)
+                ax[d - 3] = 1.0
+                R = wl.quat_to_mat(st["obj_pose"][:, :4])
+                Rn = np.einsum("ab,nbc->nac", wl.axis_angle_mat(ax, sgn * h), R)
+                s["obj_pose"][:, :4] = wl.mat_to_quat(Rn)
+            pair.append(s)
+        states.append(pair)
+    keep = np.ones(sc.n_taxels, bool)
+    for pair in states:
+        for s in pair:
+            keep &= np.all(oracle.signature(sc, s) == sig0, axis=1)
+    mask = keep.astype(np.uint8)
+    _, g = oracle.grad(sc, st, wa, wb, sel_env=sel, mask=mask)
+    fd = np.stack([(oracle.loss(sc, p[0], wa, wb, sel_env=sel, mask=mask)
+                    - oracle.loss(sc, p[1], wa, wb, sel_env=sel, mask=mask)) / (2 * h) for p in states], 1)
+    num = np.linalg.norm(g[:, :6] - fd, axis=1)
+    assert np.all(num <= 1e-5 * np.linalg.norm(g[:, :6], axis=1)), num / np.linalg.norm(g[:, :6], axis=1)
