@@ -1,0 +1,244 @@
+"""Benchmark of the MI355X tactile force field (one JSON line on stdout).
+
+Workload: the roofline shape -- 8192 environments x 2 pads x 80x100 taxels
+(1.31e8 taxel evaluations per step) against eight objects voxelized at 256^3
+(FP32), seeded poses with ~70% of taxels in contact, velocities uniform in
+[-0.1, 0.1] m/s.  A step is one pass of the whole path: per-pad prologue,
+the per-taxel force field with SoA outputs, per-pad wrench.
+
+Also reported:
+* roofline of the dominant kernel (k_force_fwd): algorithmic bytes per launch
+  / its average duration from HIP events recorded around it on its stream
+  during the timed steps;
+* cpu_baseline: the FP64 oracle on the host cores;
+* batched_vs_plain: the uneven batch (4096 envs, pads {20x25, 40x50, 80x100},
+  grids {64,128,256}^3 x 8 objects) as one persistent launch per substep vs
+  one plain launch per (pad, grid) group, both captured as HIP graphs of 100
+  substeps, with the per-taxel outputs of the two compared.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "taxel force evals/sec at 1 GPU + % HBM roofline; batched vs plain speedup at 1e-4 rel"
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(scene):
+    """Compulsory bytes of one step: 40 B/taxel of outputs written once, the
+    template read once, per-pad pose/twist in and wrench out, per-env pose,
+    twist and parameters in."""
+    T = scene.n_taxels
+    tmpl = 12 * int(scene.tmpl_offset[-1])
+    per_inst = (7 + 6 + 6) * 4
+    per_env = (7 + 6 + 4) * 4
+    return 40 * T + tmpl + per_inst * scene.n_inst + per_env * scene.n_env
+
+
+def run_main(args, torch, api, wl, autotune):
+    t0 = time.time()
+    sc = wl.make_c3()
+    log(f"c3 scene: {sc.n_env} envs, {sc.n_inst} pads, {sc.n_taxels} taxels ({time.time() - t0:.1f}s)")
+    plan = api.Plan(sc)
+    st = plan.state(sc.state())
+    out = plan.new_outputs()
+    tun = None
+    if not args.no_tune:
+        t1 = time.time()
+        res = autotune.autotune(plan, sc, st, out, reps=5, tag="c3")
+        tun = res["tuning"]
+        log(f"autotune: {tun} {res['ms']:.4f} ms ({'cached' if res['cached'] else 'searched'}, {time.time() - t1:.1f}s)")
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan.forward(st, out)
+    torch.cuda.synchronize()
+    plan.timer_start(args.steps)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.forward(st, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kms = plan.timer_read(args.steps)
+    plan.timer_start(0)
+    ms_step = wall * 1e3 / args.steps
+    value = sc.n_taxels * args.steps / wall
+    B = algorithmic_bytes(sc)
+    k_avg = float(np.mean(kms))
+    achieved = B / (k_avg * 1e-3)
+    contact = float((out["depth"] > 0).float().mean().item())
+    log(f"{ms_step:.4f} ms/step, kernel {k_avg:.4f} ms, {achieved / 1e9:.1f} GB/s, contact {contact:.3f}")
+    return dict(scene=sc, plan=plan, state=st, out=out, tuning=tun or plan.tuning, ms_step=ms_step,
+                value=value, kernel_ms=k_avg, kernel_ms_all=kms, bytes=B, achieved=achieved, contact=contact)
+
+
+def run_cpu_baseline(sc, budget_threads):
+    import oracle
+    st = oracle.state64(sc)
+    threads = max(1, min(budget_threads, os.cpu_count() or 1))
+    sel1 = np.arange(0, sc.n_inst, 16, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.force_field(sc, st, sel=sel1, nthreads=1)
+    t1 = time.perf_counter() - t0
+    n1 = int(np.diff(sc.tmpl_offset)[sc.inst_tmpl[sel1]].sum())
+    t0 = time.perf_counter()
+    oracle.force_field(sc, st, nthreads=threads)
+    tN = time.perf_counter() - t0
+    return {"value": sc.n_taxels / tN, "unit": "taxel-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 C++ oracle (g++ -O2, OpenMP over pads): the full roofline-shape step "
+                      f"({sc.n_taxels} taxels) on {threads} threads in {tN:.2f} s; 1 thread on every 16th pad "
+                      f"({n1} taxels) in {t1:.2f} s = {n1 / t1:.3e} taxel-evals/s",
+            "single_thread_value": n1 / t1}
+
+
+def run_batched_vs_plain(args, torch, api, wl, autotune):
+    t0 = time.time()
+    sc = wl.make_c4()
+    S = sc.obj_pose_steps.shape[0]
+    log(f"c4 scene: {sc.n_env} envs, {sc.n_inst} pads, {sc.n_taxels} taxels/substep, {S} substeps "
+        f"({time.time() - t0:.1f}s)")
+    # batched: one plan, persistent schedules only, autotuned
+    plan = api.Plan(sc, dict(tile_taxels=2048, schedule=2, order=2))
+    states = [plan.state(sc.state(s)) for s in range(S)]
+    tmp = plan.new_outputs()
+    if not args.no_tune:
+        res = autotune.autotune(plan, sc, states[0], tmp, reps=5, schedules=(1, 2), tag="c4-batched")
+        log(f"batched autotune: {res['tuning']} {res['ms']:.4f} ms")
+    out = plan.new_outputs()
+    wrench = torch.empty(S, sc.n_inst, 6, device=plan.device)
+    outs = [dict(out, wrench=wrench[s]) for s in range(S)]
+    g_b = api.SubstepGraph(plan, states, outs)
+    # plain: one default plan per (pad resolution, grid size) group, all
+    # groups launched in every substep (one graph, substep-major)
+    groups = wl.c4_groups(sc)
+    subs = [wl.subset_scene(sc, g) for g in groups]
+    plains, p_states, p_outs, pouts = [], [], [], []
+    for sub in subs:
+        p = api.Plan(sub)
+        po = p.new_outputs()
+        pw = torch.empty(S, sub.n_inst, 6, device=p.device)
+        plains.append(p)
+        p_states.append([p.state(sub.state(s)) for s in range(S)])
+        p_outs.append([dict(po, wrench=pw[s]) for s in range(S)])
+        pouts.append((po, pw))
+    graphs_p = [api.SubstepGraph(plains, p_states, p_outs)]
+    torch.cuda.synchronize()
+
+    def time_graphs(gs, reps):
+        for g in gs:
+            g.launch()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            for g in gs:
+                g.launch()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = args.batched_reps
+    ms_b = time_graphs([g_b], reps)
+    ms_p = time_graphs(graphs_p, reps)
+    log(f"batched {ms_b:.3f} ms / {S} substeps, plain {ms_p:.3f} ms")
+    # parity: per-taxel outputs of the last substep and all substep wrenches
+    off_all = plan.offsets()
+    max_rel = 0.0
+    bitwise = True
+    for sub, (po, pw) in zip(subs, pouts):
+        insts = sub.meta["insts"]
+        rows = np.concatenate([np.arange(off_all[i], off_all[i + 1]) for i in insts])
+        r = torch.as_tensor(rows, device=plan.device)
+        for k in ("depth",):
+            bitwise &= bool(torch.equal(out[k][r], po[k]))
+        for k in ("normal", "fn", "ft"):
+            bitwise &= bool(torch.equal(out[k][:, r], po[k]))
+        wb = wrench[:, torch.as_tensor(insts, device=plan.device)]
+        fmag = (torch.linalg.vector_norm(po["fn"] + po["ft"], dim=0))
+        scale = max(float(fmag.sum().item()) / max(sub.n_inst, 1), 1e-9)
+        max_rel = max(max_rel, float((wb - pw).abs().max().item()) / scale)
+    res = {"speedup": ms_p / ms_b, "batched_ms_per_substep": ms_b / S, "plain_ms_per_substep": ms_p / S,
+           "substeps": S, "taxel_evals_per_substep": sc.n_taxels, "plain_launch_groups": len(subs),
+           "batched_tuning": plan.tuning, "per_taxel_bitwise_equal": bitwise,
+           "wrench_max_rel_diff": max_rel, "tolerance": 1e-4,
+           "batched_taxel_evals_per_s": sc.n_taxels * S / (ms_b * 1e-3)}
+    for g in graphs_p:
+        g.close()
+    g_b.close()
+    for p in plains:
+        p.close()
+    plan.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=5)
+    ap.add_argument("--threads", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (environments shard "
+              f"across GPUs without exchange; only the single-GPU shard is built here).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2408_06506_amd import api, autotune
+    from paper_2408_06506_amd import workloads as wl
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    m = run_main(args, torch, api, wl, autotune)
+    sc = m["scene"]
+    traffic = None
+    roof = {"bound": "hbm", "achieved": m["achieved"] / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": m["achieved"] / HBM_PEAK, "traffic": traffic, "kernel": "k_force_fwd",
+            "kernel_avg_ms": m["kernel_ms"], "algorithmic_bytes_per_launch": m["bytes"],
+            "bytes_per_taxel": m["bytes"] / sc.n_taxels}
+    m["plan"].close()
+    del m["out"]
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched:
+        batched = run_batched_vs_plain(args, torch, api, wl, autotune)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = run_cpu_baseline(sc, args.threads)
+        log(f"oracle {cpu['value']:.3e} taxel-evals/s on {cpu['cores']} threads")
+    line = {
+        "metric": METRIC, "value": m["value"], "unit": "taxel-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "roofline shape: 8192 envs x 2 pads x 80x100 taxels (1.31e8 taxel evals/step), "
+                               "8 analytic objects voxelized at 256^3 FP32, ~70% of taxels in contact",
+                   "n_env": sc.n_env, "n_pads": sc.n_inst, "taxels_per_step": sc.n_taxels,
+                   "contact_fraction": m["contact"], "tuning": m["tuning"], "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

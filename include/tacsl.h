@@ -1,0 +1,256 @@
+/*
+ * tacsl.h -- C-ABI of libtacsl, the MI355X (gfx950) tactile force field.
+ *
+ * The library evaluates the penalty-based tactile force field of the TacSL
+ * paper, Section III-C ("Normal/Shear Force-Field Computation"): for every
+ * tactile point ("taxel") of every elastomer pad, in every simulated
+ * environment at once, it
+ *   1. moves the taxel into the object frame,
+ *   2. queries the object's voxelized signed-distance field (SDF) with
+ *      trilinear interpolation to get the interpenetration distance d,
+ *   3. takes the contact normal n from finite-difference gradients of the SDF,
+ *   4. applies  f_n = (-k_n + k_d d_dot) d n  and
+ *      f_t = -(v_t/|v_t|) min(k_t |v_t|, mu |f_n|),  d_dot = n . x_dot,
+ *   5. writes per-taxel depth, normal and forces and each pad's net force and
+ *      torque.
+ * The SDFs are computed before simulation and queried every step (Section
+ * III-C); the force field is a post-processing step after each dynamics step
+ * (notation appendix); contact parameters are randomized per environment
+ * (Section V-A, Appendix C); each environment may hold several pads (two
+ * fingers, Section V-B).
+ *
+ * Conventions (all entry points)
+ *  - Units: metres, seconds, newtons.  FP32 inputs and outputs.
+ *  - Poses: [qw qx qy qz tx ty tz], world frame; quaternions need not be
+ *    normalized (they are normalized internally in FP64).
+ *  - Twists: [vx vy vz wx wy wz], world frame; v is the velocity of the body
+ *    origin.
+ *  - Signed distance: negative inside the object.  d = phi; contact where
+ *    phi < 0 inside the grid's node box; the reported depth is -phi >= 0.
+ *    n = normalized finite-difference gradient, pointing out of the object.
+ *    x_dot = velocity of the taxel minus velocity of the coincident object
+ *    point.  v_t = x_dot - (n . x_dot) n.  When |grad| < 1e-6 the normal and
+ *    both forces are zero.
+ *  - Outputs are in the pad frame; torque is about the pad origin.
+ *  - Global taxel index = inst_offset[i] + k (instance-major; k indexes the
+ *    instance's template).  tacsl_plan_offsets returns inst_offset.
+ *  - Pointers marked "host" are read during the call; pointers marked
+ *    "device" must stay valid while the plan (or graph) uses them.  The
+ *    library never frees caller memory.
+ *  - Every function returns an int status: TACSL_OK (0) or a negative
+ *    tacsl_status code.  Host-side validation happens before any launch; on
+ *    error nothing is launched and no output is touched.  Device-side
+ *    anomalies are reported as bits in the optional device status word.
+ *    No exception crosses the ABI and nothing aborts.
+ */
+#ifndef TACSL_H_
+#define TACSL_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TACSL_ABI_VERSION 1
+
+typedef enum {
+  TACSL_OK = 0,
+  TACSL_ERR_NULL_ARG = -1,     /* a required pointer is NULL */
+  TACSL_ERR_SHAPE = -2,        /* counts/offsets inconsistent (non-monotone, negative, empty grid) */
+  TACSL_ERR_RANGE = -3,        /* an id or value out of range (bad index, spacing <= 0, non-finite) */
+  TACSL_ERR_HIP = -4,          /* a HIP runtime call failed */
+  TACSL_ERR_ALLOC = -5,        /* device or host allocation failed (plan creation only) */
+  TACSL_ERR_UNSUPPORTED = -6,  /* valid but beyond this build's limits (grid > 2^28 nodes, ...) */
+  TACSL_ERR_STATE = -7         /* call not valid for this object (e.g. graph of a destroyed plan) */
+} tacsl_status;
+
+/* Bits OR-ed into tacsl_outputs.status / tacsl_grads.status by the kernels. */
+#define TACSL_DEV_NONFINITE_POSE 0x1u /* a pose, twist or parameter is NaN/Inf: that pad outputs zeros */
+#define TACSL_DEV_ZERO_QUAT 0x2u      /* a quaternion has zero norm: that pad outputs zeros */
+
+/* Scene: everything that stays fixed across steps.  Read at plan creation.
+ *   n_env   environments (>= 0); n_inst pads (instances, >= 0);
+ *   n_tmpl  pad templates; n_sdf object grids.
+ *   inst_env  host [n_inst]    environment of each pad, in [0, n_env)
+ *   inst_tmpl host [n_inst]    template of each pad, in [0, n_tmpl)
+ *   env_sdf   host [n_env]     object grid of each environment, in [0, n_sdf)
+ *   tmpl_offset host [n_tmpl+1] prefix sums of template sizes; [0] = 0, non-decreasing
+ *   tmpl_xyz  device [3][T_tmpl] FP32 SoA taxel positions in the pad frame
+ *             (T_tmpl = tmpl_offset[n_tmpl]); the pad plane faces +z towards the object
+ *   sdf_dims  host [n_sdf][3]  nodes per axis (nx, ny, nz), each >= 2, product <= 2^28 - 1
+ *   sdf_origin host [n_sdf][3] position of node (0,0,0) in the object frame
+ *   sdf_spacing host [n_sdf]   isotropic node spacing h > 0
+ *   sdf_offset host [n_sdf]    element offset of each grid in sdf_data
+ *   sdf_data  device           node values (FP32 metres), x fastest: (k*ny + j)*nx + i
+ * The plan copies what it needs: tmpl_xyz must stay valid for the plan's
+ * lifetime; sdf_data is only read at plan creation. */
+typedef struct {
+  int32_t n_env, n_inst, n_tmpl, n_sdf;
+  const int32_t* inst_env;
+  const int32_t* inst_tmpl;
+  const int32_t* env_sdf;
+  const int64_t* tmpl_offset;
+  const float* tmpl_xyz;
+  const int32_t* sdf_dims;
+  const float* sdf_origin;
+  const float* sdf_spacing;
+  const int64_t* sdf_offset;
+  const float* sdf_data;
+} tacsl_scene_desc;
+
+/* Launch shape and work-list choices (chosen by the autotuner).
+ *   block        threads per workgroup: 64, 128, 256 or 512 (0 -> 256)
+ *   tile_taxels  taxels per tile; 0 -> one tile per pad; else >= 64
+ *   schedule     0: one workgroup per tile; 1: persistent workgroups, static
+ *                stride over the tile list; 2: persistent, dynamic queue
+ *   grid         persistent workgroups for schedules 1-2 (0 -> 8 per CU)
+ *   order        0: instance-major; 1: XCD-aware (tiles of one object grid
+ *                kept on one XCD's L2); 2: longest tiles first */
+typedef struct {
+  int32_t block, tile_taxels, schedule, grid, order;
+} tacsl_tuning;
+
+/* Per-step state (device, FP32).  obj_pose_delta may be NULL; when given the
+ * object pose used is R_o <- Exp(dtheta) R_o, t_o <- t_o + dt (world frame),
+ * the perturbation the pose gradient is taken against.
+ *   pad_pose [n_inst][7], obj_pose [n_env][7], pad_twist [n_inst][6],
+ *   obj_twist [n_env][6], params [n_env][4] = (k_n, k_d, k_t, mu),
+ *   obj_pose_delta [n_env][6] = (dt, dtheta). */
+typedef struct {
+  const float* pad_pose;
+  const float* obj_pose;
+  const float* pad_twist;
+  const float* obj_twist;
+  const float* params;
+  const float* obj_pose_delta;
+} tacsl_state;
+
+/* Outputs (device, FP32, caller-owned; T = total taxels):
+ *   depth [T] (>= 0), normal [3][T], fn [3][T], ft [3][T] (pad frame),
+ *   wrench [n_inst][6] = (F, torque about the pad origin), pad frame,
+ *   status: optional device uint32 word; bits are OR-ed in, never cleared. */
+typedef struct {
+  float* depth;
+  float* normal;
+  float* fn;
+  float* ft;
+  float* wrench;
+  uint32_t* status;
+} tacsl_outputs;
+
+/* Reverse mode of L = sum_k (w_fn[:,k] . f_n,k + w_ft[:,k] . f_t,k).
+ *   w_fn, w_ft  device [3][T] upstream weights (dL/df_n, dL/df_t)
+ *   g_obj_pose  device [n_env][6]: dL/d(dt, dtheta) of the object pose
+ *               perturbation t_o <- t_o + dt, R_o <- Exp(dtheta) R_o (world),
+ *               evaluated at the state's obj_pose_delta (0 when NULL)
+ *   g_obj_twist device [n_env][6]: dL/d(v_o, w_o); the gradient w.r.t. the
+ *               relative velocity of the pads is its negative
+ *   g_params    device [n_env][4]: dL/d(k_n, k_d, k_t, mu)
+ * Outputs are overwritten (not accumulated). */
+typedef struct {
+  const float* w_fn;
+  const float* w_ft;
+  float* g_obj_pose;
+  float* g_obj_twist;
+  float* g_params;
+  uint32_t* status;
+} tacsl_grads;
+
+typedef struct {
+  int64_t n_taxels;          /* T */
+  int64_t n_tiles;
+  int32_t n_env, n_inst;
+  int32_t cu_count;          /* compute units of the plan's device */
+  int32_t xcd_count;         /* XCDs assumed by the XCD-aware order */
+  int64_t prepared_bytes;    /* device bytes of the prepared SDF pool */
+  int64_t workspace_bytes;   /* device bytes of the plan's other buffers */
+  tacsl_tuning tuning;       /* resolved tuning (defaults filled in) */
+} tacsl_plan_info;
+
+typedef struct tacsl_plan_s* tacsl_plan;
+typedef struct tacsl_graph_s* tacsl_graph;
+
+/* Version of this ABI (TACSL_ABI_VERSION). */
+int tacsl_abi_version(void);
+
+/* Human-readable name of a status code; never NULL. */
+const char* tacsl_status_string(int status);
+
+/* Host-only check of a scene description (no GPU needed).  Checks counts,
+ * ids, offsets, grid sizes and spacings; does not dereference the device
+ * pointers (only checks that they are non-NULL when needed). */
+int tacsl_validate_scene(const tacsl_scene_desc* desc);
+
+/* Host-only construction of the tile work list the plan would use (no GPU
+ * needed), for inspection and tests.  Tiles are numbered instance-major:
+ * tile t covers taxels [tile_k0[t], tile_k0[t] + tile_count[t]) of pad
+ * tile_inst[t]; every pad has at least one tile (an empty pad has one tile of
+ * 0 taxels).  exec_order[s] is the tile run in execution slot s (a
+ * permutation).  Pass NULL arrays to query *n_tiles only; otherwise each
+ * array holds max_tiles entries and TACSL_ERR_SHAPE is returned if the list
+ * is longer.  xcd_count is the number of XCDs the order assumes (8 on MI355X). */
+int tacsl_build_worklist(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, int32_t xcd_count,
+                         int64_t max_tiles, int64_t* n_tiles, int32_t* tile_inst, int32_t* tile_k0,
+                         int32_t* tile_count, int32_t* exec_order);
+
+/* Create a plan on the current HIP device: validates the scene, builds the
+ * instance offsets and work list, and prepares the SDF pool (node values plus
+ * central-difference gradient channels, one-sided on grid faces).  Allocates
+ * device memory and synchronizes; not for use inside graph capture.
+ * tuning may be NULL (defaults).  On error *out is NULL. */
+int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, tacsl_plan* out);
+
+/* Replace the plan's tuning (rebuilds the work list; allocates; synchronizes). */
+int tacsl_plan_set_tuning(tacsl_plan plan, const tacsl_tuning* tuning);
+
+int tacsl_plan_get_info(tacsl_plan plan, tacsl_plan_info* info);
+
+/* Copy the instance offsets (host int64 [n_inst+1]). */
+int tacsl_plan_offsets(tacsl_plan plan, int64_t* host_inst_offset);
+
+/* Forward force field, enqueued on `stream` (asynchronous; no allocation, no
+ * host synchronization, capturable in a HIP graph).  All state and output
+ * pointers except obj_pose_delta and status are required when n_inst > 0. */
+int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, hipStream_t stream);
+
+/* Reverse mode (hand-written adjoint with recomputation of the forward),
+ * enqueued on `stream`; same asynchrony rules as tacsl_force_field. */
+int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* grads,
+                               hipStream_t stream);
+
+/* Capture n_steps forward evaluations of n_plans plans into one HIP graph,
+ * substep-major: for s in [0, n_steps), for p in [0, n_plans), plan p runs
+ * with states[s*n_plans + p] and outs[s*n_plans + p] (host arrays of structs
+ * whose device pointers are baked into the graph).  Plans must be distinct.
+ * The graph holds a reference to the plans' buffers: destroy it before any of
+ * its plans. */
+int tacsl_graph_create(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_state* states,
+                       const tacsl_outputs* outs, tacsl_graph* out);
+
+/* Replay the captured steps on `stream`. */
+int tacsl_graph_launch(tacsl_graph graph, hipStream_t stream);
+
+int tacsl_graph_destroy(tacsl_graph graph);
+
+/* Instrumentation: record a HIP event pair around the main kernel (forward
+ * k_force_fwd or adjoint k_force_bwd) of each of the next `capacity` calls on
+ * this plan, on the stream of the call.  capacity = 0 stops recording and
+ * releases the events.  Recording is skipped inside graph capture.  Creates
+ * events (allocates): call outside capture and timed regions. */
+int tacsl_plan_timer_start(tacsl_plan plan, int32_t capacity);
+
+/* Wait for the recorded events and copy the kernel durations in milliseconds
+ * of the calls recorded since tacsl_plan_timer_start (host float [max]);
+ * *n receives the number recorded (<= max). */
+int tacsl_plan_timer_read(tacsl_plan plan, int32_t max, int32_t* n, float* ms);
+
+/* Release the plan's device memory (synchronizes its device).  NULL is a no-op. */
+int tacsl_plan_destroy(tacsl_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TACSL_H_ */

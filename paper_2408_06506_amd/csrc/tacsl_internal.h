@@ -1,0 +1,121 @@
+// Internal layouts shared by the plan builder (tacsl_plan.cpp) and the
+// kernels (tacsl_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+namespace tacsl {
+
+// Static per-pad record, built at plan creation (device, read-only).
+struct InstStatic {
+  const float4* grid;   // prepared nodes (phi, dphi/dx, dphi/dy, dphi/dz) of the pad's object
+  int64_t tmpl_off;     // first taxel of the pad's template within the template rows
+  int64_t out_off;      // global taxel index of the pad's first taxel
+  int32_t nx, ny, nz;   // grid nodes per axis
+  int32_t env;          // environment of the pad
+  int32_t count;        // taxels on the pad
+  uint32_t grid_bytes;  // bytes of the prepared grid (< 2^32)
+  float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
+};
+
+// Per-step per-pad record written by the prologue (FP64 math, FP32 store).
+//   grid coordinates of a taxel:  u = A x_p + b
+//   pad-frame normal:             n = R^T n_o   (R = object-from-pad rotation)
+//   pad-frame relative velocity:  x_dot = V + W x x_p
+struct InstXf {
+  float A[9];
+  float b[3];
+  float R[9];
+  float V[3];
+  float W[3];
+  float prm[4];  // k_n, k_d, k_t, mu
+  uint32_t ok;   // 0 when the pad's inputs were rejected (then A = 0, b = -1)
+};
+
+// One unit of work: taxels [k0, k0 + count) of pad `inst`.
+struct Tile {
+  int32_t inst, k0, count, pad_;
+};
+
+struct PrologueArgs {
+  const float* pad_pose;
+  const float* obj_pose;
+  const float* pad_twist;
+  const float* obj_twist;
+  const float* params;
+  const float* obj_pose_delta;  // may be null
+  const InstStatic* stat;
+  InstXf* xf;
+  int32_t n_inst;
+  uint32_t* status;  // may be null
+  int32_t* queue;    // dynamic-schedule counter, reset to 0 here
+};
+
+struct FwdArgs {
+  const Tile* tiles;
+  const int32_t* order;  // execution slot -> tile id
+  int32_t n_tiles;
+  int32_t dynamic;       // 1: persistent dynamic queue
+  int32_t* queue;
+  const InstStatic* stat;
+  const InstXf* xf;
+  const float* tmpl;     // [3][tmpl_T]
+  int64_t tmpl_T;
+  float* depth;          // [T]
+  float* normal;         // [3][T]
+  float* fn;             // [3][T]
+  float* ft;             // [3][T]
+  int64_t T;
+  float* partial;        // [n_tiles][6] wrench partials (the wrench itself when tiles == pads)
+};
+
+struct WrenchReduceArgs {
+  const int64_t* inst_tile_begin;  // [n_inst+1]
+  const float* partial;
+  float* wrench;
+  int32_t n_inst;
+};
+
+constexpr int kBwdAcc = 19;  // P1[3] P2[3] N1[3] U1[3] U2[3] (k_n k_d k_t mu)
+
+struct BwdArgs {
+  const Tile* tiles;
+  const int32_t* order;
+  int32_t n_tiles;
+  int32_t dynamic;
+  int32_t* queue;
+  const InstStatic* stat;
+  const InstXf* xf;
+  const float* tmpl;
+  int64_t tmpl_T;
+  const float* w_fn;  // [3][T]
+  const float* w_ft;  // [3][T]
+  int64_t T;
+  double* partial;    // [n_tiles][kBwdAcc]
+};
+
+struct GradReduceArgs {
+  const int32_t* env_inst_begin;   // [n_env+1]
+  const int32_t* env_inst;         // pads of each environment, ascending
+  const int64_t* inst_tile_begin;  // [n_inst+1]
+  const double* partial;           // [n_tiles][kBwdAcc]
+  const InstStatic* stat;
+  const float* pad_pose;
+  const float* obj_pose;
+  const float* obj_twist;
+  const float* obj_pose_delta;     // may be null
+  float* g_obj_pose;               // [n_env][6]
+  float* g_obj_twist;              // [n_env][6]
+  float* g_params;                 // [n_env][4]
+  int32_t n_env;
+};
+
+hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h,
+                               uint32_t* bad_count, hipStream_t stream);
+hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream);
+hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream);
+hipError_t launch_wrench_reduce(const WrenchReduceArgs& a, hipStream_t stream);
+hipError_t launch_backward(const BwdArgs& a, int block, int grid, hipStream_t stream);
+hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t stream);
+
+}  // namespace tacsl

@@ -1,0 +1,653 @@
+// HIP kernels of the tactile force field for gfx950 (MI355X).
+//
+// The method is the penalty force field of the TacSL paper, Section III-C:
+// query the object's SDF at every tactile point (trilinear), take the
+// contact normal from finite-difference SDF gradients, and apply
+//   f_n = (-k_n + k_d d_dot) d n,   f_t = -(v_t/|v_t|) min(k_t |v_t|, mu |f_n|),
+// with d_dot = n . x_dot (chain rule of Section III-C).
+//
+// Kernels
+//   k_prepare_grid  once per plan: node value + nodal finite-difference
+//                   gradient channels as one float4 per node.
+//   k_prologue      per pad, FP64: relative pose and twist, folded into an
+//                   affine map taxel -> grid coordinates (FP32 record).
+//   k_force_fwd     per tile of taxels: the whole per-taxel path, SoA stores,
+//                   per-tile wrench partial (fixed-order reduction).
+//   k_wrench_reduce pads split over several tiles: sum partials in tile order.
+//   k_force_bwd     hand-written adjoint with recomputation of the forward.
+//   k_grad_reduce   per environment, FP64: partials -> world-frame gradients.
+//
+// Design notes (gfx950): wave64, one taxel per lane per iteration; template
+// positions and outputs are SoA so every load/store instruction moves 256
+// contiguous bytes per wave; the eight float4 corner nodes of a taxel's cell
+// are gathered through a bounds-checked buffer resource (an out-of-range
+// offset reads zeros instead of faulting); per-pad constants live in scalar
+// registers; reductions are fixed-order (deterministic, no float atomics).
+#include <hip/hip_runtime.h>
+
+#include "tacsl_internal.h"
+
+namespace tacsl {
+namespace {
+
+constexpr int kBufferFlags = 0x00020000;  // raw 32-bit dword access, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float4* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(p), (short)0, (int)bytes, kBufferFlags);
+}
+
+__device__ __forceinline__ float4 load_node(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// SDF preparation: (phi, G) per node, G = nodal finite differences (central
+// inside, one-sided on the faces).  Counts non-finite node values.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_prepare_grid(const float* __restrict__ phi, float4* __restrict__ out,
+                                                      int nx, int ny, int nz, float h,
+                                                      uint32_t* __restrict__ bad) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % nx);
+    const int j = (int)((idx / nx) % ny);
+    const int k = (int)(idx / ((int64_t)nx * ny));
+    const float p = phi[idx];
+    const int il = i > 0 ? i - 1 : 0, ih = i < nx - 1 ? i + 1 : nx - 1;
+    const int jl = j > 0 ? j - 1 : 0, jh = j < ny - 1 ? j + 1 : ny - 1;
+    const int kl = k > 0 ? k - 1 : 0, kh = k < nz - 1 ? k + 1 : nz - 1;
+    const int64_t row = ((int64_t)k * ny + j) * nx;
+    const float gx = (phi[row + ih] - phi[row + il]) / ((float)(ih - il) * h);
+    const float gy = (phi[((int64_t)k * ny + jh) * nx + i] - phi[((int64_t)k * ny + jl) * nx + i]) /
+                     ((float)(jh - jl) * h);
+    const float gz = (phi[((int64_t)kh * ny + j) * nx + i] - phi[((int64_t)kl * ny + j) * nx + i]) /
+                     ((float)(kh - kl) * h);
+    if (!isfinite(p)) atomicAdd(bad, 1u);
+    out[idx] = make_float4(p, gx, gy, gz);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prologue (FP64): per pad, object-from-pad rotation R, the affine map to grid
+// coordinates u = A x + b (A = R/h, b = (R_o^T (t_p - t_o) - origin)/h) and
+// the pad-frame relative velocity field x_dot = V + W x x_p with
+//   V = R_p^T [(v_p - v_o) - w_o x (t_p - t_o)],  W = R_p^T (w_p - w_o).
+// ---------------------------------------------------------------------------
+__device__ bool quat_to_R(const float* q, double R[9], uint32_t& bits) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  double n2 = w * w + x * x + y * y + z * z;
+  if (!(n2 > 0.0)) {
+    bits |= 0x2u;
+    return false;
+  }
+  double inv = 1.0 / sqrt(n2);
+  w *= inv; x *= inv; y *= inv; z *= inv;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+  return true;
+}
+
+// Rotation matrix of the rotation vector p (Rodrigues; series for tiny angles).
+__device__ void rotvec_to_R(const double p[3], double R[9]) {
+  const double t2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+  double a, b;
+  if (t2 < 1e-12) {
+    a = 1.0 - t2 / 6.0;
+    b = 0.5 - t2 / 24.0;
+  } else {
+    const double t = sqrt(t2);
+    a = sin(t) / t;
+    b = (1.0 - cos(t)) / t2;
+  }
+  const double K[9] = {0, -p[2], p[1], p[2], 0, -p[0], -p[1], p[0], 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double k2 = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+      R[3 * i + j] = (i == j ? 1.0 : 0.0) + a * K[3 * i + j] + b * k2;
+    }
+}
+
+__device__ bool all_finite(const float* p, int n) {
+  bool ok = true;
+  for (int i = 0; i < n; ++i) ok &= isfinite(p[i]);
+  return ok;
+}
+
+// Object world pose after the optional perturbation (FP64).
+__device__ bool object_pose(const float* obj_pose, const float* delta, double Ro[9], double to[3],
+                            uint32_t& bits) {
+  if (!quat_to_R(obj_pose, Ro, bits)) return false;
+  for (int a = 0; a < 3; ++a) to[a] = obj_pose[4 + a];
+  if (delta) {
+    const double th[3] = {delta[3], delta[4], delta[5]};
+    double E[9], M[9];
+    rotvec_to_R(th, E);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[3 * i + j] = E[3 * i] * Ro[j] + E[3 * i + 1] * Ro[3 + j] + E[3 * i + 2] * Ro[6 + j];
+    for (int i = 0; i < 9; ++i) Ro[i] = M[i];
+    for (int a = 0; a < 3; ++a) to[a] += delta[a];
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && a.queue) *a.queue = 0;
+  if (i >= a.n_inst) return;
+  const InstStatic st = a.stat[i];
+  const int e = st.env;
+  const float* pp = a.pad_pose + 7 * (int64_t)i;
+  const float* op = a.obj_pose + 7 * (int64_t)e;
+  const float* pt = a.pad_twist + 6 * (int64_t)i;
+  const float* ot = a.obj_twist + 6 * (int64_t)e;
+  const float* pr = a.params + 4 * (int64_t)e;
+  const float* dl = a.obj_pose_delta ? a.obj_pose_delta + 6 * (int64_t)e : nullptr;
+  uint32_t bits = 0;
+  bool ok = all_finite(pp, 7) && all_finite(op, 7) && all_finite(pt, 6) && all_finite(ot, 6) &&
+            all_finite(pr, 4) && (dl == nullptr || all_finite(dl, 6));
+  if (!ok) bits |= 0x1u;
+  double Rp[9], Ro[9], to[3];
+  if (ok) ok = quat_to_R(pp, Rp, bits);
+  if (ok) ok = object_pose(op, dl, Ro, to, bits);
+  InstXf x;
+  if (ok) {
+    const double tp[3] = {pp[4], pp[5], pp[6]};
+    const double d[3] = {tp[0] - to[0], tp[1] - to[1], tp[2] - to[2]};
+    double R[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) R[3 * r + c] = Ro[r] * Rp[c] + Ro[3 + r] * Rp[3 + c] + Ro[6 + r] * Rp[6 + c];
+    const double top[3] = {Ro[0] * d[0] + Ro[3] * d[1] + Ro[6] * d[2], Ro[1] * d[0] + Ro[4] * d[1] + Ro[7] * d[2],
+                           Ro[2] * d[0] + Ro[5] * d[1] + Ro[8] * d[2]};
+    const double h = st.h;
+    const double org[3] = {st.ox, st.oy, st.oz};
+    for (int k = 0; k < 9; ++k) {
+      x.A[k] = (float)(R[k] / h);
+      x.R[k] = (float)R[k];
+    }
+    for (int r = 0; r < 3; ++r) x.b[r] = (float)((top[r] - org[r]) / h);
+    const double wo[3] = {ot[3], ot[4], ot[5]};
+    const double dv[3] = {pt[0] - ot[0] - (wo[1] * d[2] - wo[2] * d[1]), pt[1] - ot[1] - (wo[2] * d[0] - wo[0] * d[2]),
+                          pt[2] - ot[2] - (wo[0] * d[1] - wo[1] * d[0])};
+    const double dw[3] = {pt[3] - ot[3], pt[4] - ot[4], pt[5] - ot[5]};
+    for (int r = 0; r < 3; ++r) {
+      x.V[r] = (float)(Rp[r] * dv[0] + Rp[3 + r] * dv[1] + Rp[6 + r] * dv[2]);
+      x.W[r] = (float)(Rp[r] * dw[0] + Rp[3 + r] * dw[1] + Rp[6 + r] * dw[2]);
+    }
+    for (int k = 0; k < 4; ++k) x.prm[k] = pr[k];
+    x.ok = 1;
+  } else {
+    for (int k = 0; k < 9; ++k) { x.A[k] = 0.f; x.R[k] = 0.f; }
+    for (int k = 0; k < 3; ++k) { x.b[k] = -1.f; x.V[k] = 0.f; x.W[k] = 0.f; }
+    for (int k = 0; k < 4; ++k) x.prm[k] = 0.f;
+    x.ok = 0;
+  }
+  a.xf[i] = x;
+  if (bits && a.status) atomicOr(a.status, bits);
+}
+
+// ---------------------------------------------------------------------------
+// Per-taxel forward (shared by the forward and the adjoint kernels).
+// ---------------------------------------------------------------------------
+struct TaxelFwd {
+  bool contact;  // inside the node box and phi < 0
+  bool force;    // contact and |g|^2 >= 1e-12
+  float ux, uy, uz;
+  float tx, ty, tz;
+  float4 c[8];   // corner nodes, index dx + 2 dy + 4 dz
+  float phi;
+  float gx, gy, gz, r;
+  float nox, noy, noz;
+  float n[3];
+  float v[3];
+  float dd, s;
+  float vt[3];
+  float vtn, cap;
+  bool stick;
+  float fn[3], ft[3];
+};
+
+__device__ __forceinline__ float tri(float c0, float c1, float c2, float c3, float c4, float c5, float c6, float c7,
+                                     float tx, float ty, float tz) {
+  const float a0 = lerp(c0, c1, tx), a1 = lerp(c2, c3, tx), a2 = lerp(c4, c5, tx), a3 = lerp(c6, c7, tx);
+  return lerp(lerp(a0, a1, ty), lerp(a2, a3, ty), tz);
+}
+
+__device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic& st, __amdgpu_buffer_rsrc_t rs,
+                                              float px, float py, float pz, TaxelFwd& f) {
+  f.contact = false;
+  f.force = false;
+  f.ux = fmaf(x.A[0], px, fmaf(x.A[1], py, fmaf(x.A[2], pz, x.b[0])));
+  f.uy = fmaf(x.A[3], px, fmaf(x.A[4], py, fmaf(x.A[5], pz, x.b[1])));
+  f.uz = fmaf(x.A[6], px, fmaf(x.A[7], py, fmaf(x.A[8], pz, x.b[2])));
+  const bool in = (f.ux >= 0.f) && (f.ux <= (float)(st.nx - 1)) && (f.uy >= 0.f) &&
+                  (f.uy <= (float)(st.ny - 1)) && (f.uz >= 0.f) && (f.uz <= (float)(st.nz - 1));
+  if (!in) return;
+  const int cx = min((int)floorf(f.ux), st.nx - 2);
+  const int cy = min((int)floorf(f.uy), st.ny - 2);
+  const int cz = min((int)floorf(f.uz), st.nz - 2);
+  f.tx = f.ux - (float)cx;
+  f.ty = f.uy - (float)cy;
+  f.tz = f.uz - (float)cz;
+  const uint32_t sy = 16u * (uint32_t)st.nx;
+  const uint32_t sz = sy * (uint32_t)st.ny;
+  const uint32_t o = 16u * (uint32_t)((cz * st.ny + cy) * st.nx + cx);
+  f.c[0] = load_node(rs, o);
+  f.c[1] = load_node(rs, o + 16u);
+  f.c[2] = load_node(rs, o + sy);
+  f.c[3] = load_node(rs, o + sy + 16u);
+  f.c[4] = load_node(rs, o + sz);
+  f.c[5] = load_node(rs, o + sz + 16u);
+  f.c[6] = load_node(rs, o + sz + sy);
+  f.c[7] = load_node(rs, o + sz + sy + 16u);
+  const float4* c = f.c;
+  f.phi = tri(c[0].x, c[1].x, c[2].x, c[3].x, c[4].x, c[5].x, c[6].x, c[7].x, f.tx, f.ty, f.tz);
+  if (!(f.phi < 0.f)) return;
+  f.contact = true;
+  f.gx = tri(c[0].y, c[1].y, c[2].y, c[3].y, c[4].y, c[5].y, c[6].y, c[7].y, f.tx, f.ty, f.tz);
+  f.gy = tri(c[0].z, c[1].z, c[2].z, c[3].z, c[4].z, c[5].z, c[6].z, c[7].z, f.tx, f.ty, f.tz);
+  f.gz = tri(c[0].w, c[1].w, c[2].w, c[3].w, c[4].w, c[5].w, c[6].w, c[7].w, f.tx, f.ty, f.tz);
+  const float gg = fmaf(f.gx, f.gx, fmaf(f.gy, f.gy, f.gz * f.gz));
+  if (!(gg >= 1e-12f)) return;
+  f.force = true;
+  f.r = rsqrtf(gg);
+  f.nox = f.gx * f.r;
+  f.noy = f.gy * f.r;
+  f.noz = f.gz * f.r;
+  // pad-frame normal n = R^T n_o
+  f.n[0] = fmaf(x.R[0], f.nox, fmaf(x.R[3], f.noy, x.R[6] * f.noz));
+  f.n[1] = fmaf(x.R[1], f.nox, fmaf(x.R[4], f.noy, x.R[7] * f.noz));
+  f.n[2] = fmaf(x.R[2], f.nox, fmaf(x.R[5], f.noy, x.R[8] * f.noz));
+  // relative velocity x_dot = V + W x p
+  f.v[0] = x.V[0] + fmaf(x.W[1], pz, -x.W[2] * py);
+  f.v[1] = x.V[1] + fmaf(x.W[2], px, -x.W[0] * pz);
+  f.v[2] = x.V[2] + fmaf(x.W[0], py, -x.W[1] * px);
+  f.dd = fmaf(f.n[0], f.v[0], fmaf(f.n[1], f.v[1], f.n[2] * f.v[2]));
+  f.s = fmaf(x.prm[1], f.dd, -x.prm[0]) * f.phi;
+  for (int a = 0; a < 3; ++a) {
+    f.fn[a] = f.s * f.n[a];
+    f.vt[a] = fmaf(-f.dd, f.n[a], f.v[a]);
+  }
+  f.vtn = sqrtf(fmaf(f.vt[0], f.vt[0], fmaf(f.vt[1], f.vt[1], f.vt[2] * f.vt[2])));
+  f.cap = x.prm[3] * fabsf(f.s);
+  f.stick = x.prm[2] * f.vtn <= f.cap;
+  const float coef = f.stick ? -x.prm[2] : -(f.cap / f.vtn);
+  for (int a = 0; a < 3; ++a) f.ft[a] = coef * f.vt[a];
+}
+
+// Next execution slot of a tile loop (uniform across the workgroup).
+template <int BLOCK>
+__device__ __forceinline__ int next_slot(int slot, int dynamic, int32_t* queue, int* s_next) {
+  if (dynamic) {
+    if (threadIdx.x == 0) *s_next = (int)gridDim.x + atomicAdd(queue, 1);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*s_next);
+  }
+  __syncthreads();
+  return slot + (int)gridDim.x;
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernel.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_force_fwd(FwdArgs a) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ float red[NW][6];
+  __shared__ int s_next;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int slot = blockIdx.x;
+  while (slot < a.n_tiles) {
+    const int tid = a.order[slot];
+    const Tile tl = a.tiles[tid];
+    const InstStatic st = a.stat[tl.inst];
+    const InstXf x = a.xf[tl.inst];
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
+    const float* tx = a.tmpl + st.tmpl_off + tl.k0;
+    const float* ty = tx + a.tmpl_T;
+    const float* tz = ty + a.tmpl_T;
+    const int64_t ob = st.out_off + tl.k0;
+    float* o_d = a.depth + ob;
+    float* o_n0 = a.normal + ob;
+    float* o_n1 = o_n0 + a.T;
+    float* o_n2 = o_n1 + a.T;
+    float* o_f0 = a.fn + ob;
+    float* o_f1 = o_f0 + a.T;
+    float* o_f2 = o_f1 + a.T;
+    float* o_t0 = a.ft + ob;
+    float* o_t1 = o_t0 + a.T;
+    float* o_t2 = o_t1 + a.T;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
+      const float px = tx[k], py = ty[k], pz = tz[k];
+      TaxelFwd f;
+      taxel_forward(x, st, rs, px, py, pz, f);
+      float dep = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+      float fn0 = 0.f, fn1 = 0.f, fn2 = 0.f, ft0 = 0.f, ft1 = 0.f, ft2 = 0.f;
+      if (f.contact) dep = -f.phi;
+      if (f.force) {
+        n0 = f.n[0]; n1 = f.n[1]; n2 = f.n[2];
+        fn0 = f.fn[0]; fn1 = f.fn[1]; fn2 = f.fn[2];
+        ft0 = f.ft[0]; ft1 = f.ft[1]; ft2 = f.ft[2];
+      }
+      o_d[k] = dep;
+      o_n0[k] = n0; o_n1[k] = n1; o_n2[k] = n2;
+      o_f0[k] = fn0; o_f1[k] = fn1; o_f2[k] = fn2;
+      o_t0[k] = ft0; o_t1[k] = ft1; o_t2[k] = ft2;
+      const float F0 = fn0 + ft0, F1 = fn1 + ft1, F2 = fn2 + ft2;
+      acc[0] += F0;
+      acc[1] += F1;
+      acc[2] += F2;
+      acc[3] += fmaf(py, F2, -pz * F1);
+      acc[4] += fmaf(pz, F0, -px * F2);
+      acc[5] += fmaf(px, F1, -py * F0);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float v = wave_sum(acc[c]);
+      if (lane == 0) red[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      float s = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
+      a.partial[6 * (int64_t)tid + threadIdx.x] = s;
+    }
+    slot = next_slot<BLOCK>(slot, a.dynamic, a.queue, &s_next);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wrench_reduce(WrenchReduceArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_inst) return;
+  float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int64_t t = a.inst_tile_begin[i]; t < a.inst_tile_begin[i + 1]; ++t)
+    for (int c = 0; c < 6; ++c) s[c] += a.partial[6 * t + c];
+  for (int c = 0; c < 6; ++c) a.wrench[6 * (int64_t)i + c] = s[c];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint kernel: recompute the forward per taxel, then reverse mode of
+// L = w_fn . f_n + w_ft . f_t.  Per-lane accumulators (pad/object frames):
+//   P1 = sum x_dot_bar, P2 = sum x_dot_bar x x_p, N1 = sum n x n_bar,
+//   U1 = sum u_bar,     U2 = sum u_bar x u       (grid coordinates),
+//   and the four parameter adjoints.  k_grad_reduce maps them to the world.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_force_bwd(BwdArgs a) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ double red[NW][kBwdAcc];
+  __shared__ int s_next;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int slot = blockIdx.x;
+  while (slot < a.n_tiles) {
+    const int tid = a.order[slot];
+    const Tile tl = a.tiles[tid];
+    const InstStatic st = a.stat[tl.inst];
+    const InstXf x = a.xf[tl.inst];
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
+    const float* tx = a.tmpl + st.tmpl_off + tl.k0;
+    const float* ty = tx + a.tmpl_T;
+    const float* tz = ty + a.tmpl_T;
+    const int64_t ob = st.out_off + tl.k0;
+    const float* wa0 = a.w_fn + ob;
+    const float* wa1 = wa0 + a.T;
+    const float* wa2 = wa1 + a.T;
+    const float* wb0 = a.w_ft + ob;
+    const float* wb1 = wb0 + a.T;
+    const float* wb2 = wb1 + a.T;
+    const float kn = x.prm[0], kd = x.prm[1], kt = x.prm[2], mu = x.prm[3];
+    float acc[kBwdAcc];
+#pragma unroll
+    for (int c = 0; c < kBwdAcc; ++c) acc[c] = 0.f;
+    for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
+      const float px = tx[k], py = ty[k], pz = tz[k];
+      TaxelFwd f;
+      taxel_forward(x, st, rs, px, py, pz, f);
+      if (!f.force) continue;
+      const float A[3] = {wa0[k], wa1[k], wa2[k]};
+      const float B[3] = {wb0[k], wb1[k], wb2[k]};
+      // f_n = s n
+      float nb[3], vb[3], vtb[3];
+      for (int c = 0; c < 3; ++c) nb[c] = f.s * A[c];
+      float sb = A[0] * f.n[0] + A[1] * f.n[1] + A[2] * f.n[2];
+      float ktb = 0.f, mub = 0.f;
+      if (f.stick) {  // f_t = -k_t v_t
+        for (int c = 0; c < 3; ++c) vtb[c] = -kt * B[c];
+        ktb = -(B[0] * f.vt[0] + B[1] * f.vt[1] + B[2] * f.vt[2]);
+      } else {  // f_t = -cap v_t / |v_t|
+        const float iv = 1.f / f.vtn;
+        const float q = f.cap * iv;
+        const float vh[3] = {f.vt[0] * iv, f.vt[1] * iv, f.vt[2] * iv};
+        const float bv = B[0] * vh[0] + B[1] * vh[1] + B[2] * vh[2];
+        for (int c = 0; c < 3; ++c) vtb[c] = -q * (B[c] - bv * vh[c]);
+        const float capb = -bv;
+        mub = capb * fabsf(f.s);
+        sb += capb * mu * (f.s < 0.f ? -1.f : 1.f);
+      }
+      // v_t = x_dot - d_dot n
+      float ddb = -(vtb[0] * f.n[0] + vtb[1] * f.n[1] + vtb[2] * f.n[2]);
+      for (int c = 0; c < 3; ++c) {
+        vb[c] = vtb[c];
+        nb[c] -= f.dd * vtb[c];
+      }
+      // s = (-k_n + k_d d_dot) phi
+      const float knb = -f.phi * sb;
+      const float kdb = f.dd * f.phi * sb;
+      ddb += kd * f.phi * sb;
+      const float phib = (kd * f.dd - kn) * sb;
+      // d_dot = n . x_dot
+      for (int c = 0; c < 3; ++c) {
+        nb[c] += ddb * f.v[c];
+        vb[c] += ddb * f.n[c];
+      }
+      // x_dot = V + W x p
+      acc[0] += vb[0]; acc[1] += vb[1]; acc[2] += vb[2];
+      acc[3] += vb[1] * pz - vb[2] * py;
+      acc[4] += vb[2] * px - vb[0] * pz;
+      acc[5] += vb[0] * py - vb[1] * px;
+      // rotation of the normal: N1 += n x n_bar
+      acc[6] += f.n[1] * nb[2] - f.n[2] * nb[1];
+      acc[7] += f.n[2] * nb[0] - f.n[0] * nb[2];
+      acc[8] += f.n[0] * nb[1] - f.n[1] * nb[0];
+      // n = R^T n_o  ->  n_o_bar = R n_bar
+      const float nob0 = x.R[0] * nb[0] + x.R[1] * nb[1] + x.R[2] * nb[2];
+      const float nob1 = x.R[3] * nb[0] + x.R[4] * nb[1] + x.R[5] * nb[2];
+      const float nob2 = x.R[6] * nb[0] + x.R[7] * nb[1] + x.R[8] * nb[2];
+      // n_o = g / |g|
+      const float pr = nob0 * f.nox + nob1 * f.noy + nob2 * f.noz;
+      const float gb0 = f.r * (nob0 - pr * f.nox);
+      const float gb1 = f.r * (nob1 - pr * f.noy);
+      const float gb2 = f.r * (nob2 - pr * f.noz);
+      // phi, g trilinear in t: corner scalars Q = phi_bar Phi_c + g_bar . G_c
+      float Q[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        Q[c] = phib * f.c[c].x + gb0 * f.c[c].y + gb1 * f.c[c].z + gb2 * f.c[c].w;
+      const float ub0 = lerp(lerp(Q[1] - Q[0], Q[3] - Q[2], f.ty), lerp(Q[5] - Q[4], Q[7] - Q[6], f.ty), f.tz);
+      const float ub1 = lerp(lerp(Q[2] - Q[0], Q[3] - Q[1], f.tx), lerp(Q[6] - Q[4], Q[7] - Q[5], f.tx), f.tz);
+      const float ub2 = lerp(lerp(Q[4] - Q[0], Q[5] - Q[1], f.tx), lerp(Q[6] - Q[2], Q[7] - Q[3], f.tx), f.ty);
+      acc[9] += ub0; acc[10] += ub1; acc[11] += ub2;
+      acc[12] += ub1 * f.uz - ub2 * f.uy;
+      acc[13] += ub2 * f.ux - ub0 * f.uz;
+      acc[14] += ub0 * f.uy - ub1 * f.ux;
+      acc[15] += knb; acc[16] += kdb; acc[17] += ktb; acc[18] += mub;
+    }
+#pragma unroll
+    for (int c = 0; c < kBwdAcc; ++c) {
+      const double v = wave_sum((double)acc[c]);
+      if (lane == 0) red[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kBwdAcc) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
+      a.partial[kBwdAcc * (int64_t)tid + threadIdx.x] = s;
+    }
+    slot = next_slot<BLOCK>(slot, a.dynamic, a.queue, &s_next);
+  }
+}
+
+__device__ void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ void matvec(const double R[9], const double v[3], double o[3]) {
+  for (int r = 0; r < 3; ++r) o[r] = R[3 * r] * v[0] + R[3 * r + 1] * v[1] + R[3 * r + 2] * v[2];
+}
+
+// Per environment (FP64): world-frame gradients
+//   dt     = -R_o U1/h + (R_p P1) x w_o
+//   dtheta =  R_p N1 + R_o X2,  X2 = (U1 x origin)/h + U2
+//   dv_o   = -R_p P1
+//   dw_o   =  R_p (P2 + P1 x c_p),  c_p = R_p^T (t_p - t_o)
+// summed over the environment's pads; then the rotation block is mapped from
+// a left perturbation of the composed pose to the input delta: J_l(delta)^T.
+__global__ __launch_bounds__(64) void k_grad_reduce(GradReduceArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n_env) return;
+  double gp[6] = {0, 0, 0, 0, 0, 0}, gt[6] = {0, 0, 0, 0, 0, 0}, gk[4] = {0, 0, 0, 0};
+  uint32_t bits = 0;
+  double Ro[9], to[3];
+  const float* dl = a.obj_pose_delta ? a.obj_pose_delta + 6 * (int64_t)e : nullptr;
+  const bool ok_o = object_pose(a.obj_pose + 7 * (int64_t)e, dl, Ro, to, bits);
+  const double wo[3] = {a.obj_twist[6 * (int64_t)e + 3], a.obj_twist[6 * (int64_t)e + 4],
+                        a.obj_twist[6 * (int64_t)e + 5]};
+  for (int32_t q = a.env_inst_begin[e]; q < a.env_inst_begin[e + 1] && ok_o; ++q) {
+    const int i = a.env_inst[q];
+    double S[kBwdAcc];
+    for (int c = 0; c < kBwdAcc; ++c) S[c] = 0.0;
+    for (int64_t t = a.inst_tile_begin[i]; t < a.inst_tile_begin[i + 1]; ++t)
+      for (int c = 0; c < kBwdAcc; ++c) S[c] += a.partial[kBwdAcc * t + c];
+    double Rp[9];
+    const float* pp = a.pad_pose + 7 * (int64_t)i;
+    if (!quat_to_R(pp, Rp, bits)) continue;
+    const InstStatic st = a.stat[i];
+    const double h = st.h;
+    const double org[3] = {st.ox, st.oy, st.oz};
+    const double P1[3] = {S[0], S[1], S[2]}, P2[3] = {S[3], S[4], S[5]}, N1[3] = {S[6], S[7], S[8]};
+    const double U1[3] = {S[9], S[10], S[11]}, U2[3] = {S[12], S[13], S[14]};
+    double X1[3], X2[3], tmp[3], tmp2[3];
+    for (int c = 0; c < 3; ++c) X1[c] = U1[c] / h;
+    cross3(U1, org, tmp);
+    for (int c = 0; c < 3; ++c) X2[c] = tmp[c] / h + U2[c];
+    double RpP1[3], RoX1[3], RoX2[3], RpN1[3];
+    matvec(Rp, P1, RpP1);
+    matvec(Ro, X1, RoX1);
+    matvec(Ro, X2, RoX2);
+    matvec(Rp, N1, RpN1);
+    cross3(RpP1, wo, tmp);
+    for (int c = 0; c < 3; ++c) {
+      gp[c] += -RoX1[c] + tmp[c];
+      gp[3 + c] += RpN1[c] + RoX2[c];
+      gt[c] += -RpP1[c];
+    }
+    const double d[3] = {pp[4] - to[0], pp[5] - to[1], pp[6] - to[2]};
+    const double cp[3] = {Rp[0] * d[0] + Rp[3] * d[1] + Rp[6] * d[2], Rp[1] * d[0] + Rp[4] * d[1] + Rp[7] * d[2],
+                          Rp[2] * d[0] + Rp[5] * d[1] + Rp[8] * d[2]};
+    cross3(P1, cp, tmp);
+    for (int c = 0; c < 3; ++c) tmp[c] += P2[c];
+    matvec(Rp, tmp, tmp2);
+    for (int c = 0; c < 3; ++c) gt[3 + c] += tmp2[c];
+    for (int c = 0; c < 4; ++c) gk[c] += S[15 + c];
+  }
+  if (dl) {  // dL/d(delta_theta) = J_l(delta_theta)^T dL/d(left perturbation)
+    const double p[3] = {dl[3], dl[4], dl[5]};
+    const double t2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    double a1, a2;
+    if (t2 < 1e-12) {
+      a1 = 0.5 - t2 / 24.0;
+      a2 = 1.0 / 6.0 - t2 / 120.0;
+    } else {
+      const double t = sqrt(t2);
+      a1 = (1.0 - cos(t)) / t2;
+      a2 = (t - sin(t)) / (t2 * t);
+    }
+    // J_l = I + a1 K + a2 K^2, K = [p]x ; J_l^T g = g - a1 K g + a2 K^2 g
+    const double g[3] = {gp[3], gp[4], gp[5]};
+    double Kg[3], KKg[3];
+    cross3(p, g, Kg);
+    cross3(p, Kg, KKg);
+    for (int c = 0; c < 3; ++c) gp[3 + c] = g[c] - a1 * Kg[c] + a2 * KKg[c];
+  }
+  for (int c = 0; c < 6; ++c) {
+    a.g_obj_pose[6 * (int64_t)e + c] = (float)gp[c];
+    a.g_obj_twist[6 * (int64_t)e + c] = (float)gt[c];
+  }
+  for (int c = 0; c < 4; ++c) a.g_params[4 * (int64_t)e + c] = (float)gk[c];
+}
+
+}  // namespace
+
+hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h, uint32_t* bad,
+                               hipStream_t stream) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_prepare_grid, dim3((unsigned)blocks), dim3(256), 0, stream, phi, out, nx, ny, nz, h, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream) {
+  const int blocks = a.n_inst > 0 ? (a.n_inst + 63) / 64 : 1;
+  hipLaunchKernelGGL(k_prologue, dim3(blocks), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL(k_force_fwd<64>, dim3(grid), dim3(64), 0, stream, a); break;
+    case 128: hipLaunchKernelGGL(k_force_fwd<128>, dim3(grid), dim3(128), 0, stream, a); break;
+    case 256: hipLaunchKernelGGL(k_force_fwd<256>, dim3(grid), dim3(256), 0, stream, a); break;
+    case 512: hipLaunchKernelGGL(k_force_fwd<512>, dim3(grid), dim3(512), 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wrench_reduce(const WrenchReduceArgs& a, hipStream_t stream) {
+  const int blocks = (a.n_inst + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wrench_reduce, dim3(blocks), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const BwdArgs& a, int block, int grid, hipStream_t stream) {
+  switch (block) {
+    case 64: hipLaunchKernelGGL(k_force_bwd<64>, dim3(grid), dim3(64), 0, stream, a); break;
+    case 128: hipLaunchKernelGGL(k_force_bwd<128>, dim3(grid), dim3(128), 0, stream, a); break;
+    case 256: hipLaunchKernelGGL(k_force_bwd<256>, dim3(grid), dim3(256), 0, stream, a); break;
+    case 512: hipLaunchKernelGGL(k_force_bwd<512>, dim3(grid), dim3(512), 0, stream, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t stream) {
+  const int blocks = (a.n_env + 63) / 64;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_reduce, dim3(blocks), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace tacsl

@@ -1,0 +1,699 @@
+// Host side of libtacsl: scene validation, work-list construction, plans,
+// the extern "C" entry points of include/tacsl.h, and substep graphs.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "tacsl.h"
+#include "tacsl_internal.h"
+
+using tacsl::InstStatic;
+using tacsl::InstXf;
+using tacsl::Tile;
+
+namespace {
+
+constexpr int64_t kMaxGridNodes = (int64_t(1) << 28) - 1;  // 16 B per prepared node, offsets < 2^32
+constexpr int64_t kMaxTemplate = int64_t(1) << 30;
+constexpr int kXcdCount = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin across them
+
+int64_t tmpl_count(const tacsl_scene_desc& d, int i) {
+  const int p = d.inst_tmpl[i];
+  return d.tmpl_offset[p + 1] - d.tmpl_offset[p];
+}
+
+int validate(const tacsl_scene_desc* d) {
+  if (!d) return TACSL_ERR_NULL_ARG;
+  if (d->n_env < 0 || d->n_inst < 0 || d->n_tmpl < 0 || d->n_sdf < 0) return TACSL_ERR_SHAPE;
+  if (d->n_inst > 0 && (d->n_env < 1 || d->n_tmpl < 1 || d->n_sdf < 1)) return TACSL_ERR_SHAPE;
+  if (d->n_inst > 0 && (!d->inst_env || !d->inst_tmpl)) return TACSL_ERR_NULL_ARG;
+  if (d->n_env > 0 && !d->env_sdf) return TACSL_ERR_NULL_ARG;
+  if (d->n_tmpl > 0 && !d->tmpl_offset) return TACSL_ERR_NULL_ARG;
+  if (d->n_sdf > 0 && (!d->sdf_dims || !d->sdf_origin || !d->sdf_spacing || !d->sdf_offset || !d->sdf_data))
+    return TACSL_ERR_NULL_ARG;
+  if (d->n_tmpl > 0) {
+    if (d->tmpl_offset[0] != 0) return TACSL_ERR_SHAPE;
+    for (int p = 0; p < d->n_tmpl; ++p) {
+      const int64_t c = d->tmpl_offset[p + 1] - d->tmpl_offset[p];
+      if (c < 0) return TACSL_ERR_SHAPE;
+      if (c > kMaxTemplate) return TACSL_ERR_UNSUPPORTED;
+    }
+    if (d->tmpl_offset[d->n_tmpl] > 0 && !d->tmpl_xyz) return TACSL_ERR_NULL_ARG;
+  }
+  for (int e = 0; e < d->n_env; ++e)
+    if (d->env_sdf[e] < 0 || d->env_sdf[e] >= d->n_sdf) return TACSL_ERR_RANGE;
+  for (int i = 0; i < d->n_inst; ++i) {
+    if (d->inst_env[i] < 0 || d->inst_env[i] >= d->n_env) return TACSL_ERR_RANGE;
+    if (d->inst_tmpl[i] < 0 || d->inst_tmpl[i] >= d->n_tmpl) return TACSL_ERR_RANGE;
+  }
+  for (int g = 0; g < d->n_sdf; ++g) {
+    const int32_t* n = d->sdf_dims + 3 * g;
+    if (n[0] < 2 || n[1] < 2 || n[2] < 2) return TACSL_ERR_SHAPE;
+    const int64_t nodes = (int64_t)n[0] * n[1] * n[2];
+    if (nodes > kMaxGridNodes) return TACSL_ERR_UNSUPPORTED;
+    const float h = d->sdf_spacing[g];
+    if (!(h > 0.f) || !std::isfinite(h)) return TACSL_ERR_RANGE;
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(d->sdf_origin[3 * g + a])) return TACSL_ERR_RANGE;
+    if (d->sdf_offset[g] < 0) return TACSL_ERR_RANGE;
+  }
+  int64_t T = 0;
+  for (int i = 0; i < d->n_inst; ++i) {
+    T += tmpl_count(*d, i);
+    if (T > (int64_t(1) << 40)) return TACSL_ERR_UNSUPPORTED;
+  }
+  return TACSL_OK;
+}
+
+int resolve_tuning(const tacsl_tuning* in, int cu_count, tacsl_tuning* out) {
+  tacsl_tuning t = {0, 0, 0, 0, 0};
+  if (in) t = *in;
+  if (t.block == 0) t.block = 256;
+  if (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512) return TACSL_ERR_RANGE;
+  if (t.tile_taxels < 0 || (t.tile_taxels > 0 && t.tile_taxels < 64) || t.tile_taxels > kMaxTemplate)
+    return TACSL_ERR_RANGE;
+  if (t.schedule < 0 || t.schedule > 2) return TACSL_ERR_RANGE;
+  if (t.order < 0 || t.order > 2) return TACSL_ERR_RANGE;
+  if (t.grid < 0) return TACSL_ERR_RANGE;
+  if (t.grid == 0) t.grid = std::max(1, cu_count) * 8;
+  *out = t;
+  return TACSL_OK;
+}
+
+// Tiles are numbered instance-major (every pad has >= 1 tile); `order` maps
+// execution slots to tile ids.
+int make_worklist(const tacsl_scene_desc& d, const tacsl_tuning& t, int xcd, std::vector<Tile>& tiles,
+                  std::vector<int32_t>& order, std::vector<int64_t>& inst_tile_begin) {
+  tiles.clear();
+  order.clear();
+  inst_tile_begin.assign((size_t)d.n_inst + 1, 0);
+  for (int i = 0; i < d.n_inst; ++i) {
+    inst_tile_begin[i] = (int64_t)tiles.size();
+    const int64_t cnt = tmpl_count(d, i);
+    if (cnt == 0) {
+      tiles.push_back(Tile{i, 0, 0, 0});
+      continue;
+    }
+    const int64_t tsz = t.tile_taxels > 0 ? t.tile_taxels : cnt;
+    for (int64_t k0 = 0; k0 < cnt; k0 += tsz)
+      tiles.push_back(Tile{i, (int32_t)k0, (int32_t)std::min(tsz, cnt - k0), 0});
+    if ((int64_t)tiles.size() > (int64_t)INT32_MAX) return TACSL_ERR_UNSUPPORTED;
+  }
+  inst_tile_begin[d.n_inst] = (int64_t)tiles.size();
+  const int32_t n = (int32_t)tiles.size();
+  order.resize(n);
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](int32_t tid) { return (int64_t)std::max(tiles[tid].count, 1); };
+  if (t.order == 2) {
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+  } else if (t.order == 1 && n > 0) {
+    // group by object grid, cut into xcd contiguous segments of equal cost,
+    // interleave so that slot s runs on XCD s % xcd while segments last
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return d.env_sdf[d.inst_env[tiles[a].inst]] < d.env_sdf[d.inst_env[tiles[b].inst]];
+    });
+    int64_t total = 0;
+    for (int32_t tid : order) total += cost(tid);
+    std::vector<std::vector<int32_t>> seg((size_t)xcd);
+    int64_t acc = 0;
+    int x = 0;
+    for (int32_t tid : order) {
+      while (x < xcd - 1 && acc >= (total * (x + 1)) / xcd) ++x;
+      seg[x].push_back(tid);
+      acc += cost(tid);
+    }
+    order.clear();
+    std::vector<size_t> pos((size_t)xcd, 0);
+    bool more = true;
+    while (more) {
+      more = false;
+      for (int s = 0; s < xcd; ++s)
+        if (pos[s] < seg[s].size()) {
+          order.push_back(seg[s][pos[s]++]);
+          more = true;
+        }
+    }
+  }
+  return TACSL_OK;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct tacsl_plan_s {
+  int device = 0;
+  int32_t n_env = 0, n_inst = 0, n_tmpl = 0, n_sdf = 0;
+  int64_t T = 0;
+  int cu_count = 0;
+  tacsl_tuning tun{};
+  std::vector<int64_t> inst_off;
+  // scene copies needed to rebuild the work list
+  std::vector<int32_t> inst_env, inst_tmpl, env_sdf;
+  std::vector<int64_t> tmpl_offset;
+  const float* tmpl_xyz = nullptr;
+  int64_t tmpl_T = 0;
+  // device buffers
+  float4* grids = nullptr;
+  int64_t grids_bytes = 0;
+  InstStatic* d_stat = nullptr;
+  InstXf* d_xf = nullptr;
+  Tile* d_tiles = nullptr;
+  int32_t* d_order = nullptr;
+  int64_t* d_inst_tile_begin = nullptr;
+  float* d_partial = nullptr;
+  double* d_bpartial = nullptr;
+  int32_t* d_queue = nullptr;
+  int32_t* d_env_inst_begin = nullptr;
+  int32_t* d_env_inst = nullptr;
+  int64_t n_tiles = 0;
+  int64_t ws_bytes = 0;
+  int live_graphs = 0;
+  // kernel timer (instrumentation)
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int32_t timer_n = 0;
+
+  void free_timer() {
+    for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+    ev_start.clear();
+    ev_stop.clear();
+    timer_n = 0;
+  }
+  bool timing() const { return timer_n < (int32_t)ev_start.size(); }
+
+  tacsl_scene_desc desc() const {
+    tacsl_scene_desc d{};
+    d.n_env = n_env;
+    d.n_inst = n_inst;
+    d.n_tmpl = n_tmpl;
+    d.n_sdf = n_sdf;
+    d.inst_env = inst_env.data();
+    d.inst_tmpl = inst_tmpl.data();
+    d.env_sdf = env_sdf.data();
+    d.tmpl_offset = tmpl_offset.data();
+    d.tmpl_xyz = tmpl_xyz;
+    return d;
+  }
+
+  void free_worklist() {
+    dfree(d_tiles);
+    dfree(d_order);
+    dfree(d_inst_tile_begin);
+    dfree(d_partial);
+    dfree(d_bpartial);
+  }
+  void free_all() {
+    free_timer();
+    free_worklist();
+    dfree(grids);
+    dfree(d_stat);
+    dfree(d_xf);
+    dfree(d_queue);
+    dfree(d_env_inst_begin);
+    dfree(d_env_inst);
+  }
+};
+
+struct tacsl_graph_s {
+  std::vector<tacsl_plan> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
+  std::vector<Tile> tiles;
+  std::vector<int32_t> order;
+  std::vector<int64_t> itb;
+  const tacsl_scene_desc d = p->desc();
+  int rc = make_worklist(d, t, kXcdCount, tiles, order, itb);
+  if (rc != TACSL_OK) return rc;
+  p->free_worklist();
+  const size_t n = tiles.size();
+  if (dalloc(&p->d_tiles, n) != hipSuccess || dalloc(&p->d_order, n) != hipSuccess ||
+      dalloc(&p->d_inst_tile_begin, itb.size()) != hipSuccess || dalloc(&p->d_partial, 6 * n) != hipSuccess ||
+      dalloc(&p->d_bpartial, (size_t)tacsl::kBwdAcc * n) != hipSuccess) {
+    p->free_worklist();
+    return TACSL_ERR_ALLOC;
+  }
+  if (n > 0 && (hipMemcpy(p->d_tiles, tiles.data(), n * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(p->d_order, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess))
+    return TACSL_ERR_HIP;
+  if (hipMemcpy(p->d_inst_tile_begin, itb.data(), itb.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return TACSL_ERR_HIP;
+  p->n_tiles = (int64_t)n;
+  p->tun = t;
+  return TACSL_OK;
+}
+
+int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, hipStream_t stream,
+                    bool capturing) {
+  if (p->n_inst == 0) return TACSL_OK;
+  tacsl::PrologueArgs pa{};
+  pa.pad_pose = s->pad_pose;
+  pa.obj_pose = s->obj_pose;
+  pa.pad_twist = s->pad_twist;
+  pa.obj_twist = s->obj_twist;
+  pa.params = s->params;
+  pa.obj_pose_delta = s->obj_pose_delta;
+  pa.stat = p->d_stat;
+  pa.xf = p->d_xf;
+  pa.n_inst = p->n_inst;
+  pa.status = o->status;
+  pa.queue = p->d_queue;
+  if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+  const bool direct = p->n_tiles == p->n_inst;  // one tile per pad: tile id == pad id
+  tacsl::FwdArgs fa{};
+  fa.tiles = p->d_tiles;
+  fa.order = p->d_order;
+  fa.n_tiles = (int32_t)p->n_tiles;
+  fa.dynamic = p->tun.schedule == 2 ? 1 : 0;
+  fa.queue = p->d_queue;
+  fa.stat = p->d_stat;
+  fa.xf = p->d_xf;
+  fa.tmpl = p->tmpl_xyz;
+  fa.tmpl_T = p->tmpl_T;
+  fa.depth = o->depth;
+  fa.normal = o->normal;
+  fa.fn = o->fn;
+  fa.ft = o->ft;
+  fa.T = p->T;
+  fa.partial = direct ? o->wrench : p->d_partial;
+  const int grid = p->tun.schedule == 0 ? (int)p->n_tiles : (int)std::min<int64_t>(p->tun.grid, p->n_tiles);
+  const bool timed = !capturing && p->timing();
+  if (timed && hipEventRecord(p->ev_start[p->timer_n], stream) != hipSuccess) return TACSL_ERR_HIP;
+  if (tacsl::launch_forward(fa, p->tun.block, grid, stream) != hipSuccess) return TACSL_ERR_HIP;
+  if (timed) {
+    if (hipEventRecord(p->ev_stop[p->timer_n], stream) != hipSuccess) return TACSL_ERR_HIP;
+    p->timer_n++;
+  }
+  if (!direct) {
+    tacsl::WrenchReduceArgs ra{p->d_inst_tile_begin, p->d_partial, o->wrench, p->n_inst};
+    if (tacsl::launch_wrench_reduce(ra, stream) != hipSuccess) return TACSL_ERR_HIP;
+  }
+  return TACSL_OK;
+}
+
+int check_state(const tacsl_plan p, const tacsl_state* s) {
+  if (!s) return TACSL_ERR_NULL_ARG;
+  if (p->n_inst > 0 && (!s->pad_pose || !s->obj_pose || !s->pad_twist || !s->obj_twist || !s->params))
+    return TACSL_ERR_NULL_ARG;
+  return TACSL_OK;
+}
+
+int check_outputs(const tacsl_plan p, const tacsl_outputs* o) {
+  if (!o) return TACSL_ERR_NULL_ARG;
+  if (p->n_inst > 0 && (!o->wrench || (p->T > 0 && (!o->depth || !o->normal || !o->fn || !o->ft))))
+    return TACSL_ERR_NULL_ARG;
+  return TACSL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tacsl_abi_version(void) { return TACSL_ABI_VERSION; }
+
+const char* tacsl_status_string(int status) {
+  switch (status) {
+    case TACSL_OK: return "TACSL_OK";
+    case TACSL_ERR_NULL_ARG: return "TACSL_ERR_NULL_ARG: a required pointer is NULL";
+    case TACSL_ERR_SHAPE: return "TACSL_ERR_SHAPE: inconsistent counts or offsets";
+    case TACSL_ERR_RANGE: return "TACSL_ERR_RANGE: id or value out of range";
+    case TACSL_ERR_HIP: return "TACSL_ERR_HIP: HIP runtime call failed";
+    case TACSL_ERR_ALLOC: return "TACSL_ERR_ALLOC: allocation failed";
+    case TACSL_ERR_UNSUPPORTED: return "TACSL_ERR_UNSUPPORTED: beyond this build's limits";
+    case TACSL_ERR_STATE: return "TACSL_ERR_STATE: call not valid for this object";
+    default: return "TACSL_ERR_UNKNOWN";
+  }
+}
+
+int tacsl_validate_scene(const tacsl_scene_desc* desc) { return validate(desc); }
+
+int tacsl_build_worklist(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, int32_t xcd_count,
+                         int64_t max_tiles, int64_t* n_tiles, int32_t* tile_inst, int32_t* tile_k0,
+                         int32_t* tile_count, int32_t* exec_order) {
+  int rc = validate(desc);
+  if (rc != TACSL_OK) return rc;
+  if (!n_tiles) return TACSL_ERR_NULL_ARG;
+  if (xcd_count < 1) return TACSL_ERR_RANGE;
+  tacsl_tuning t;
+  rc = resolve_tuning(tuning, 1, &t);
+  if (rc != TACSL_OK) return rc;
+  std::vector<Tile> tiles;
+  std::vector<int32_t> order;
+  std::vector<int64_t> itb;
+  rc = make_worklist(*desc, t, xcd_count, tiles, order, itb);
+  if (rc != TACSL_OK) return rc;
+  *n_tiles = (int64_t)tiles.size();
+  if (!tile_inst && !tile_k0 && !tile_count && !exec_order) return TACSL_OK;
+  if (!tile_inst || !tile_k0 || !tile_count || !exec_order) return TACSL_ERR_NULL_ARG;
+  if ((int64_t)tiles.size() > max_tiles) return TACSL_ERR_SHAPE;
+  for (size_t k = 0; k < tiles.size(); ++k) {
+    tile_inst[k] = tiles[k].inst;
+    tile_k0[k] = tiles[k].k0;
+    tile_count[k] = tiles[k].count;
+    exec_order[k] = order[k];
+  }
+  return TACSL_OK;
+}
+
+int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, tacsl_plan* out) {
+  if (!out) return TACSL_ERR_NULL_ARG;
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc != TACSL_OK) return rc;
+  tacsl_plan p = new (std::nothrow) tacsl_plan_s();
+  if (!p) return TACSL_ERR_ALLOC;
+  auto fail = [&](int code) {
+    p->free_all();
+    delete p;
+    return code;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return fail(TACSL_ERR_HIP);
+  if (hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+    return fail(TACSL_ERR_HIP);
+  tacsl_tuning t;
+  rc = resolve_tuning(tuning, p->cu_count, &t);
+  if (rc != TACSL_OK) return fail(rc);
+  const tacsl_scene_desc& d = *desc;
+  p->n_env = d.n_env;
+  p->n_inst = d.n_inst;
+  p->n_tmpl = d.n_tmpl;
+  p->n_sdf = d.n_sdf;
+  p->inst_env.assign(d.inst_env, d.inst_env + d.n_inst);
+  p->inst_tmpl.assign(d.inst_tmpl, d.inst_tmpl + d.n_inst);
+  p->env_sdf.assign(d.env_sdf, d.env_sdf + d.n_env);
+  p->tmpl_offset.assign(d.tmpl_offset, d.tmpl_offset + (d.n_tmpl > 0 ? d.n_tmpl + 1 : 0));
+  p->tmpl_xyz = d.tmpl_xyz;
+  p->tmpl_T = d.n_tmpl > 0 ? d.tmpl_offset[d.n_tmpl] : 0;
+  p->inst_off.assign((size_t)d.n_inst + 1, 0);
+  for (int i = 0; i < d.n_inst; ++i) p->inst_off[i + 1] = p->inst_off[i] + tmpl_count(d, i);
+  p->T = p->inst_off[d.n_inst];
+
+  // prepared SDF pool: (phi, grad) float4 per node
+  std::vector<int64_t> gbase((size_t)d.n_sdf + 1, 0);
+  for (int g = 0; g < d.n_sdf; ++g)
+    gbase[g + 1] = gbase[g] + (int64_t)d.sdf_dims[3 * g] * d.sdf_dims[3 * g + 1] * d.sdf_dims[3 * g + 2];
+  p->grids_bytes = gbase[d.n_sdf] * (int64_t)sizeof(float4);
+  if (dalloc(&p->grids, (size_t)gbase[d.n_sdf]) != hipSuccess) return fail(TACSL_ERR_ALLOC);
+  uint32_t* d_bad = nullptr;
+  if (dalloc(&d_bad, 1) != hipSuccess) return fail(TACSL_ERR_ALLOC);
+  if (hipMemset(d_bad, 0, sizeof(uint32_t)) != hipSuccess) {
+    dfree(d_bad);
+    return fail(TACSL_ERR_HIP);
+  }
+  for (int g = 0; g < d.n_sdf; ++g) {
+    if (tacsl::launch_prepare_grid(d.sdf_data + d.sdf_offset[g], p->grids + gbase[g], d.sdf_dims[3 * g],
+                                   d.sdf_dims[3 * g + 1], d.sdf_dims[3 * g + 2], d.sdf_spacing[g], d_bad,
+                                   nullptr) != hipSuccess) {
+      dfree(d_bad);
+      return fail(TACSL_ERR_HIP);
+    }
+  }
+  uint32_t bad = 0;
+  hipError_t e = hipMemcpy(&bad, d_bad, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  dfree(d_bad);
+  if (e != hipSuccess) return fail(TACSL_ERR_HIP);
+  if (bad) return fail(TACSL_ERR_RANGE);
+
+  // static per-pad records
+  std::vector<InstStatic> st((size_t)d.n_inst);
+  for (int i = 0; i < d.n_inst; ++i) {
+    const int g = d.env_sdf[d.inst_env[i]];
+    InstStatic& s = st[i];
+    s.grid = p->grids + gbase[g];
+    s.tmpl_off = d.tmpl_offset[d.inst_tmpl[i]];
+    s.out_off = p->inst_off[i];
+    s.nx = d.sdf_dims[3 * g];
+    s.ny = d.sdf_dims[3 * g + 1];
+    s.nz = d.sdf_dims[3 * g + 2];
+    s.env = d.inst_env[i];
+    s.count = (int32_t)tmpl_count(d, i);
+    s.grid_bytes = (uint32_t)((gbase[g + 1] - gbase[g]) * (int64_t)sizeof(float4));
+    s.ox = d.sdf_origin[3 * g];
+    s.oy = d.sdf_origin[3 * g + 1];
+    s.oz = d.sdf_origin[3 * g + 2];
+    s.h = d.sdf_spacing[g];
+  }
+  // environments -> pads (ascending)
+  std::vector<int32_t> eib((size_t)d.n_env + 1, 0), ei((size_t)d.n_inst);
+  for (int i = 0; i < d.n_inst; ++i) eib[d.inst_env[i] + 1]++;
+  for (int e2 = 0; e2 < d.n_env; ++e2) eib[e2 + 1] += eib[e2];
+  {
+    std::vector<int32_t> fill(eib.begin(), eib.end() - 1);
+    for (int i = 0; i < d.n_inst; ++i) ei[fill[d.inst_env[i]]++] = i;
+  }
+  if (dalloc(&p->d_stat, st.size()) != hipSuccess || dalloc(&p->d_xf, (size_t)d.n_inst) != hipSuccess ||
+      dalloc(&p->d_queue, 1) != hipSuccess || dalloc(&p->d_env_inst_begin, eib.size()) != hipSuccess ||
+      dalloc(&p->d_env_inst, ei.size()) != hipSuccess)
+    return fail(TACSL_ERR_ALLOC);
+  if ((!st.empty() && hipMemcpy(p->d_stat, st.data(), st.size() * sizeof(InstStatic), hipMemcpyHostToDevice) !=
+                          hipSuccess) ||
+      hipMemcpy(p->d_env_inst_begin, eib.data(), eib.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      (!ei.empty() && hipMemcpy(p->d_env_inst, ei.data(), ei.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                          hipSuccess) ||
+      hipMemset(p->d_queue, 0, sizeof(int32_t)) != hipSuccess)
+    return fail(TACSL_ERR_HIP);
+  rc = install_worklist(p, t);
+  if (rc != TACSL_OK) return fail(rc);
+  p->ws_bytes = (int64_t)(st.size() * sizeof(InstStatic) + (size_t)d.n_inst * sizeof(InstXf) +
+                          (size_t)p->n_tiles * (sizeof(Tile) + sizeof(int32_t) + 6 * sizeof(float) +
+                                                tacsl::kBwdAcc * sizeof(double)) +
+                          ((size_t)d.n_inst + 1) * sizeof(int64_t) + eib.size() * 4 + ei.size() * 4 + 4);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(TACSL_ERR_HIP);
+  *out = p;
+  return TACSL_OK;
+}
+
+int tacsl_plan_set_tuning(tacsl_plan plan, const tacsl_tuning* tuning) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (plan->live_graphs > 0) return TACSL_ERR_STATE;
+  tacsl_tuning t;
+  int rc = resolve_tuning(tuning, plan->cu_count, &t);
+  if (rc != TACSL_OK) return rc;
+  if (hipDeviceSynchronize() != hipSuccess) return TACSL_ERR_HIP;
+  return install_worklist(plan, t);
+}
+
+int tacsl_plan_get_info(tacsl_plan plan, tacsl_plan_info* info) {
+  if (!plan || !info) return TACSL_ERR_NULL_ARG;
+  info->n_taxels = plan->T;
+  info->n_tiles = plan->n_tiles;
+  info->n_env = plan->n_env;
+  info->n_inst = plan->n_inst;
+  info->cu_count = plan->cu_count;
+  info->xcd_count = kXcdCount;
+  info->prepared_bytes = plan->grids_bytes;
+  info->workspace_bytes = plan->ws_bytes;
+  info->tuning = plan->tun;
+  return TACSL_OK;
+}
+
+int tacsl_plan_offsets(tacsl_plan plan, int64_t* host_inst_offset) {
+  if (!plan || !host_inst_offset) return TACSL_ERR_NULL_ARG;
+  std::memcpy(host_inst_offset, plan->inst_off.data(), plan->inst_off.size() * sizeof(int64_t));
+  return TACSL_OK;
+}
+
+int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, hipStream_t stream) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  int rc = check_state(plan, state);
+  if (rc != TACSL_OK) return rc;
+  rc = check_outputs(plan, out);
+  if (rc != TACSL_OK) return rc;
+  return enqueue_forward(plan, state, out, stream, false);
+}
+
+int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* g,
+                               hipStream_t stream) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  int rc = check_state(plan, state);
+  if (rc != TACSL_OK) return rc;
+  if (!g) return TACSL_ERR_NULL_ARG;
+  if (plan->n_env > 0 && (!g->g_obj_pose || !g->g_obj_twist || !g->g_params)) return TACSL_ERR_NULL_ARG;
+  if (plan->T > 0 && (!g->w_fn || !g->w_ft)) return TACSL_ERR_NULL_ARG;
+  if (plan->n_env == 0) return TACSL_OK;
+  if (plan->n_inst > 0) {
+    tacsl::PrologueArgs pa{};
+    pa.pad_pose = state->pad_pose;
+    pa.obj_pose = state->obj_pose;
+    pa.pad_twist = state->pad_twist;
+    pa.obj_twist = state->obj_twist;
+    pa.params = state->params;
+    pa.obj_pose_delta = state->obj_pose_delta;
+    pa.stat = plan->d_stat;
+    pa.xf = plan->d_xf;
+    pa.n_inst = plan->n_inst;
+    pa.status = g->status;
+    pa.queue = plan->d_queue;
+    if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+    tacsl::BwdArgs ba{};
+    ba.tiles = plan->d_tiles;
+    ba.order = plan->d_order;
+    ba.n_tiles = (int32_t)plan->n_tiles;
+    ba.dynamic = plan->tun.schedule == 2 ? 1 : 0;
+    ba.queue = plan->d_queue;
+    ba.stat = plan->d_stat;
+    ba.xf = plan->d_xf;
+    ba.tmpl = plan->tmpl_xyz;
+    ba.tmpl_T = plan->tmpl_T;
+    ba.w_fn = g->w_fn;
+    ba.w_ft = g->w_ft;
+    ba.T = plan->T;
+    ba.partial = plan->d_bpartial;
+    const int grid =
+        plan->tun.schedule == 0 ? (int)plan->n_tiles : (int)std::min<int64_t>(plan->tun.grid, plan->n_tiles);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return TACSL_ERR_HIP;
+    const bool timed = cap == hipStreamCaptureStatusNone && plan->timing();
+    if (timed && hipEventRecord(plan->ev_start[plan->timer_n], stream) != hipSuccess) return TACSL_ERR_HIP;
+    if (tacsl::launch_backward(ba, plan->tun.block, grid, stream) != hipSuccess) return TACSL_ERR_HIP;
+    if (timed) {
+      if (hipEventRecord(plan->ev_stop[plan->timer_n], stream) != hipSuccess) return TACSL_ERR_HIP;
+      plan->timer_n++;
+    }
+  }
+  tacsl::GradReduceArgs ga{};
+  ga.env_inst_begin = plan->d_env_inst_begin;
+  ga.env_inst = plan->d_env_inst;
+  ga.inst_tile_begin = plan->d_inst_tile_begin;
+  ga.partial = plan->d_bpartial;
+  ga.stat = plan->d_stat;
+  ga.pad_pose = state->pad_pose;
+  ga.obj_pose = state->obj_pose;
+  ga.obj_twist = state->obj_twist;
+  ga.obj_pose_delta = state->obj_pose_delta;
+  ga.g_obj_pose = g->g_obj_pose;
+  ga.g_obj_twist = g->g_obj_twist;
+  ga.g_params = g->g_params;
+  ga.n_env = plan->n_env;
+  if (tacsl::launch_grad_reduce(ga, stream) != hipSuccess) return TACSL_ERR_HIP;
+  return TACSL_OK;
+}
+
+int tacsl_graph_create(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_state* states,
+                       const tacsl_outputs* outs, tacsl_graph* out) {
+  if (!out) return TACSL_ERR_NULL_ARG;
+  *out = nullptr;
+  if (!plans || !states || !outs) return TACSL_ERR_NULL_ARG;
+  if (n_plans < 1 || n_steps < 1) return TACSL_ERR_SHAPE;
+  for (int p = 0; p < n_plans; ++p) {
+    if (!plans[p]) return TACSL_ERR_NULL_ARG;
+    for (int q = 0; q < p; ++q)
+      if (plans[q] == plans[p]) return TACSL_ERR_STATE;
+  }
+  for (int s = 0; s < n_steps; ++s)
+    for (int p = 0; p < n_plans; ++p) {
+      const int64_t k = (int64_t)s * n_plans + p;
+      int rc = check_state(plans[p], states + k);
+      if (rc != TACSL_OK) return rc;
+      rc = check_outputs(plans[p], outs + k);
+      if (rc != TACSL_OK) return rc;
+    }
+  tacsl_graph g = new (std::nothrow) tacsl_graph_s();
+  if (!g) return TACSL_ERR_ALLOC;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return TACSL_ERR_HIP;
+  }
+  int rc = TACSL_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = TACSL_ERR_HIP;
+  for (int s = 0; s < n_steps && rc == TACSL_OK; ++s)
+    for (int p = 0; p < n_plans && rc == TACSL_OK; ++p) {
+      const int64_t k = (int64_t)s * n_plans + p;
+      rc = enqueue_forward(plans[p], states + k, outs + k, cs, true);
+    }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (rc == TACSL_OK && e != hipSuccess) rc = TACSL_ERR_HIP;
+  if (rc == TACSL_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = TACSL_ERR_HIP;
+  (void)hipStreamDestroy(cs);
+  if (rc != TACSL_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    delete g;
+    return rc;
+  }
+  g->graph = graph;
+  g->plans.assign(plans, plans + n_plans);
+  for (tacsl_plan p : g->plans) p->live_graphs++;
+  *out = g;
+  return TACSL_OK;
+}
+
+int tacsl_graph_launch(tacsl_graph graph, hipStream_t stream) {
+  if (!graph || !graph->exec) return TACSL_ERR_NULL_ARG;
+  return hipGraphLaunch(graph->exec, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
+}
+
+int tacsl_graph_destroy(tacsl_graph graph) {
+  if (!graph) return TACSL_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  for (tacsl_plan p : graph->plans) p->live_graphs--;
+  delete graph;
+  return TACSL_OK;
+}
+
+int tacsl_plan_timer_start(tacsl_plan plan, int32_t capacity) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (capacity < 0) return TACSL_ERR_RANGE;
+  plan->free_timer();
+  for (int32_t k = 0; k < capacity; ++k) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) {
+      plan->free_timer();
+      return TACSL_ERR_HIP;
+    }
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      plan->free_timer();
+      return TACSL_ERR_HIP;
+    }
+    plan->ev_start.push_back(a);
+    plan->ev_stop.push_back(b);
+  }
+  return TACSL_OK;
+}
+
+int tacsl_plan_timer_read(tacsl_plan plan, int32_t max, int32_t* n, float* ms) {
+  if (!plan || !n || (max > 0 && !ms)) return TACSL_ERR_NULL_ARG;
+  const int32_t m = std::min(max, plan->timer_n);
+  for (int32_t k = 0; k < m; ++k) {
+    if (hipEventSynchronize(plan->ev_stop[k]) != hipSuccess) return TACSL_ERR_HIP;
+    if (hipEventElapsedTime(ms + k, plan->ev_start[k], plan->ev_stop[k]) != hipSuccess) return TACSL_ERR_HIP;
+  }
+  *n = m;
+  return TACSL_OK;
+}
+
+int tacsl_plan_destroy(tacsl_plan plan) {
+  if (!plan) return TACSL_OK;
+  if (plan->live_graphs > 0) return TACSL_ERR_STATE;
+  (void)hipDeviceSynchronize();
+  plan->free_all();
+  delete plan;
+  return TACSL_OK;
+}
+
+}  // extern "C"

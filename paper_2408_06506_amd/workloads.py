@@ -377,32 +377,37 @@ def _pad_frames(rng, normals, max_tilt_deg=5.0):
     return rt @ r
 
 
-def _place_pads(obj, rng, tmpl_sub, n, pen_target, frac_target=None, pen_cap=None):
-    """Pad poses in the object frame with a controlled penetration.
+def _draw_pads(obj, rng, n):
+    """Random part of pad placement: surface point, outward normal, pad frame."""
+    q, nrm = _surface_points(obj, rng, n)
+    r = _pad_frames(rng, nrm)
+    return q, nrm, r
+
+
+def _bisect_offsets(obj, tmpl_sub, q, nrm, r, pen_target, frac_target=None, pen_cap=None, iters=36):
+    """Deterministic part of pad placement (no random draws).
 
     ``tmpl_sub`` are the taxel positions (pad frame, FP64 [K,3]) used to
     measure penetration.  The pad moves along the surface normal; the offset
     is bisected so that the deepest taxel penetration equals ``pen_target``
     (or, when ``frac_target`` is given, so that that fraction of taxels is
-    inside, with the deepest penetration capped at ``pen_cap``).
+    inside, with the deepest penetration capped at ``pen_cap``).  Returns the
+    pad origins in the object frame.
     """
-    q, nrm = _surface_points(obj, rng, n)
-    r = _pad_frames(rng, nrm)
+    n = q.shape[0]
     xk = np.einsum("nij,kj->nki", r, tmpl_sub)  # (n, K, 3)
 
     def depth_stats(off):
         p = q + nrm * off[:, None]
-        pts = p[:, None, :] + xk
-        v = obj.sdf(pts)
+        v = obj.sdf(p[:, None, :] + xk)
         return -v.min(axis=1), (v < 0).mean(axis=1)
 
     def bisect(fn, target):
         lo = np.full(n, -10 * MM)  # deep
         hi = np.full(n, 10 * MM)  # clear
-        for _ in range(48):
+        for _ in range(iters):
             mid = 0.5 * (lo + hi)
-            val = fn(mid)
-            deeper = val > target
+            deeper = fn(mid) > target
             lo = np.where(deeper, mid, lo)
             hi = np.where(deeper, hi, mid)
         return 0.5 * (lo + hi)
@@ -413,7 +418,7 @@ def _place_pads(obj, rng, tmpl_sub, n, pen_target, frac_target=None, pen_cap=Non
         off_f = bisect(lambda o: depth_stats(o)[1] - 1e-9, frac_target)
         off_c = bisect(lambda o: depth_stats(o)[0], pen_cap)
         off = np.maximum(off_f, off_c)
-    return r, q + nrm * off[:, None]
+    return q + nrm * off[:, None]
 
 
 # --------------------------------------------------------------------------
@@ -534,27 +539,33 @@ def build_scene(name: str, cfg_id: int, step: int, env_obj: Sequence[str],
 
     pad_R = np.zeros((I, 3, 3))
     pad_t = np.zeros((I, 3))
-    # place pads group by (object, resolution) so the analytic SDF is vectorised
+    # place pads group by (object, resolution) so the analytic SDF is vectorised;
+    # random draws happen in a fixed sequential order, bisection runs threaded
     groups: Dict[Tuple[str, Tuple[int, int]], List[int]] = {}
     for i in range(I):
         e = inst_env[i]
         groups.setdefault((env_obj[e], tuple(env_res[e])), []).append(i)
+    jobs = []
     for (oname, res), insts in sorted(groups.items()):
         obj = OBJECTS[oname]
         t = pad_template(*res).astype(np.float64).T
         if placement_subsample:
             nx, ny = res
-            s = placement_subsample
-            ii = np.arange(0, nx, max(1, nx // s[0]))
-            jj = np.arange(0, ny, max(1, ny // s[1]))
-            idx = (jj[:, None] * nx + ii[None, :]).reshape(-1)
-            t = t[idx]
+            ii = np.arange(0, nx, max(1, nx // placement_subsample[0]))
+            jj = np.arange(0, ny, max(1, ny // placement_subsample[1]))
+            t = t[(jj[:, None] * nx + ii[None, :]).reshape(-1)]
         insts = np.asarray(insts)
         pen = rng.uniform(pen_range[0], pen_range[1], insts.size)
-        r_in, p_in = _place_pads(obj, rng, t, insts.size, pen,
-                                 frac_target=frac_target, pen_cap=pen_cap)
-        pad_R[insts] = r_in
-        pad_t[insts] = p_in
+        q, nrm, r = _draw_pads(obj, rng, insts.size)
+        jobs.append((obj, t, insts, q, nrm, r, pen))
+
+    def place(job):
+        obj, t, insts, q, nrm, r, pen = job
+        pad_R[insts] = r
+        pad_t[insts] = _bisect_offsets(obj, t, q, nrm, r, pen, frac_target=frac_target, pen_cap=pen_cap)
+
+    with _fut.ThreadPoolExecutor(max_workers=8) as ex:
+        list(ex.map(place, jobs))
     # compose to world
     Rw = np.einsum("iab,ibc->iac", R_o[inst_env], pad_R)
     tw = t_o[inst_env] + np.einsum("iab,ib->ia", R_o[inst_env], pad_t)
@@ -617,7 +628,7 @@ def make_c3(n_env: int = 8192, res=(80, 100), grid: int = 256) -> Scene:
     objs = [EIGHT_OBJECTS[e % 8] for e in range(n_env)]
     return build_scene("c3", 3, 0, objs, [grid] * n_env, [res] * n_env,
                        frac_target=0.7, pen_cap=2 * MM, vmax=0.1,
-                       placement_subsample=(20, 25))
+                       placement_subsample=(10, 12))
 
 
 C4_RES = [(20, 25), (40, 50), (80, 100)]
@@ -633,7 +644,7 @@ def make_c4(n_env: int = 4096, substeps: int = C4_SUBSTEPS, grids=C4_GRIDS) -> S
     res = [C4_RES[k] for k in rng.integers(0, 3, n_env)]
     gr = [grids[k] for k in rng.integers(0, len(grids), n_env)]
     sc = build_scene("c4", 4, 0, objs, gr, res, pen_range=(1 * MM, 1 * MM), vmax=0.1,
-                     placement_subsample=(20, 25))
+                     placement_subsample=(10, 12))
     v = sc.obj_twist[:, :3].astype(np.float64)
     base = sc.obj_pose.astype(np.float64)
     steps = np.repeat(base[None], substeps, axis=0)
@@ -683,3 +694,48 @@ def make_uneven_small(cfg_id: int = 12, n_env: int = 12, substeps: int = 3) -> S
     steps[:, :, 4:7] = base[None, :, 4:7] + v[None] * (s * C4_DT)
     sc.obj_pose_steps = steps.astype(np.float32)
     return sc
+
+
+def subset_scene(scene: Scene, envs: Sequence[int], name: Optional[str] = None) -> Scene:
+    """The environments ``envs`` of ``scene`` (with their pads, grids and
+    templates) as a scene of their own; pads keep their relative order."""
+    envs = np.asarray(envs, dtype=np.int64)
+    emap = -np.ones(scene.n_env, np.int64)
+    emap[envs] = np.arange(envs.size)
+    insts = np.flatnonzero(emap[scene.inst_env] >= 0)
+    sdf_used = np.unique(scene.env_sdf[envs])
+    smap = -np.ones(scene.n_sdf, np.int64)
+    smap[sdf_used] = np.arange(sdf_used.size)
+    tmpl_used = np.unique(scene.inst_tmpl[insts])
+    tmap = -np.ones(scene.n_tmpl, np.int64)
+    tmap[tmpl_used] = np.arange(tmpl_used.size)
+    sizes = (scene.sdf_dims[:, 0].astype(np.int64) * scene.sdf_dims[:, 1] * scene.sdf_dims[:, 2])
+    datas = [scene.sdf_data[scene.sdf_offset[g]:scene.sdf_offset[g] + sizes[g]] for g in sdf_used]
+    offs = np.concatenate([[0], np.cumsum([d.size for d in datas])[:-1]]).astype(np.int64)
+    tparts = [scene.tmpl_xyz[:, scene.tmpl_offset[p]:scene.tmpl_offset[p + 1]] for p in tmpl_used]
+    toff = np.concatenate([[0], np.cumsum([t.shape[1] for t in tparts])]).astype(np.int64)
+    sub = Scene(
+        name=name or f"{scene.name}-sub", n_env=int(envs.size), n_inst=int(insts.size),
+        inst_env=emap[scene.inst_env[insts]].astype(np.int32), inst_tmpl=tmap[scene.inst_tmpl[insts]].astype(np.int32),
+        env_sdf=smap[scene.env_sdf[envs]].astype(np.int32), tmpl_offset=toff,
+        tmpl_xyz=np.concatenate(tparts, axis=1) if tparts else np.zeros((3, 0), np.float32),
+        sdf_dims=scene.sdf_dims[sdf_used].copy(), sdf_origin=scene.sdf_origin[sdf_used].copy(),
+        sdf_spacing=scene.sdf_spacing[sdf_used].copy(), sdf_offset=offs,
+        sdf_data=np.concatenate(datas) if datas else np.zeros(0, np.float32),
+        pad_pose=scene.pad_pose[insts].copy(), obj_pose=scene.obj_pose[envs].copy(),
+        pad_twist=scene.pad_twist[insts].copy(), obj_twist=scene.obj_twist[envs].copy(),
+        params=scene.params[envs].copy(), sdf_names=[scene.sdf_names[g] for g in sdf_used] if scene.sdf_names else [],
+        tmpl_names=[scene.tmpl_names[p] for p in tmpl_used] if scene.tmpl_names else [],
+        obj_pose_steps=None if scene.obj_pose_steps is None else scene.obj_pose_steps[:, envs].copy(),
+        meta=dict(scene.meta, parent=scene.name, envs=envs, insts=insts))
+    return sub
+
+
+def c4_groups(scene: Scene):
+    """Environments of the uneven batch grouped by (pad resolution, grid size)."""
+    keys = {}
+    for e in range(scene.n_env):
+        i = int(np.flatnonzero(scene.inst_env == e)[0])
+        key = (int(np.diff(scene.tmpl_offset)[scene.inst_tmpl[i]]), tuple(scene.sdf_dims[scene.env_sdf[e]]))
+        keys.setdefault(key, []).append(e)
+    return [np.asarray(v) for _, v in sorted(keys.items())]

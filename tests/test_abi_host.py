@@ -1,0 +1,174 @@
+"""Host-side tests of the C-ABI (no GPU): exports, validation, work lists.
+
+The library loads on a machine without a GPU; only host-only entry points are
+called here (no kernel launch).
+"""
+import copy
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2408_06506_amd import _abi, api
+from paper_2408_06506_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "tacsl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tacsl_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.load()
+    names = _header_functions()
+    assert len(names) == 16
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_abi.EXPORTS) == names
+    assert lib.tacsl_abi_version() == 1
+
+
+def test_status_strings():
+    lib = _abi.load()
+    for code, name in _abi.STATUS_NAMES.items():
+        assert lib.tacsl_status_string(code).decode().startswith(name)
+    assert lib.tacsl_status_string(-99).decode() == "TACSL_ERR_UNKNOWN"
+
+
+def _uneven():
+    return wl.make_uneven_small(cfg_id=12, n_env=12, substeps=1)
+
+
+def test_valid_scenes_pass():
+    for sc in (_uneven(), wl.make_c1(0), wl.make_small(n_env=3)):
+        assert api.validate_scene(sc) == 0
+
+
+def test_null_pointers_rejected():
+    lib = _abi.load()
+    assert lib.tacsl_validate_scene(None) == -1
+    sc = _uneven()
+    assert api.validate_scene(sc, tmpl_ptr=None) == -1
+    assert api.validate_scene(sc, sdf_ptr=None) == -1
+
+
+def _mut(sc, **kw):
+    s = copy.copy(sc)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def test_invalid_descriptions_return_codes():
+    sc = _uneven()
+    # non-monotone template offsets
+    off = sc.tmpl_offset.copy()
+    off[1], off[2] = off[2], off[1]
+    assert api.validate_scene(_mut(sc, tmpl_offset=off)) == -2
+    off = sc.tmpl_offset.copy()
+    off[0] = 1
+    assert api.validate_scene(_mut(sc, tmpl_offset=off)) == -2
+    # out-of-range ids
+    ie = sc.inst_env.copy()
+    ie[3] = sc.n_env
+    assert api.validate_scene(_mut(sc, inst_env=ie)) == -3
+    ie[3] = -1
+    assert api.validate_scene(_mut(sc, inst_env=ie)) == -3
+    it = sc.inst_tmpl.copy()
+    it[0] = 99
+    assert api.validate_scene(_mut(sc, inst_tmpl=it)) == -3
+    es = sc.env_sdf.copy()
+    es[0] = sc.n_sdf
+    assert api.validate_scene(_mut(sc, env_sdf=es)) == -3
+    # grid dimension < 2
+    dims = sc.sdf_dims.copy()
+    dims[1, 2] = 1
+    assert api.validate_scene(_mut(sc, sdf_dims=dims)) == -2
+    # non-positive or non-finite spacing, non-finite origin, negative offset
+    for bad in (0.0, -1e-3, np.nan, np.inf):
+        sp = sc.sdf_spacing.copy()
+        sp[0] = bad
+        assert api.validate_scene(_mut(sc, sdf_spacing=sp)) == -3
+    org = sc.sdf_origin.copy()
+    org[0, 1] = np.nan
+    assert api.validate_scene(_mut(sc, sdf_origin=org)) == -3
+    so = sc.sdf_offset.copy()
+    so[0] = -5
+    assert api.validate_scene(_mut(sc, sdf_offset=so)) == -3
+    # grid too large for 32-bit buffer offsets (2^28 nodes of 16 B)
+    dims = sc.sdf_dims.copy()
+    dims[0] = (1024, 1024, 256)
+    assert api.validate_scene(_mut(sc, sdf_dims=dims)) == -6
+    dims[0] = (1024, 1024, 255)
+    assert api.validate_scene(_mut(sc, sdf_dims=dims)) == 0
+    # counts
+    assert api.validate_scene(_mut(sc, n_env=-1)) == -2
+
+
+def test_empty_scene_is_valid():
+    sc = _mut(_uneven(), n_inst=0, inst_env=np.zeros(0, np.int32), inst_tmpl=np.zeros(0, np.int32))
+    assert api.validate_scene(sc) == 0
+    wlst = api.build_worklist(sc)
+    assert wlst["inst"].size == 0
+
+
+def _independent_tiles(sc, tile):
+    counts = np.diff(sc.tmpl_offset)[sc.inst_tmpl]
+    out = []
+    for i, c in enumerate(counts):
+        if c == 0:
+            out.append((i, 0, 0))
+            continue
+        step = tile if tile > 0 else c
+        k = 0
+        while k < c:
+            out.append((i, k, min(step, c - k)))
+            k += step
+    return out
+
+
+@pytest.mark.parametrize("tile", [0, 64, 100, 1024])
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_worklist_covers_every_taxel_once(tile, order):
+    sc = _uneven()
+    w = api.build_worklist(sc, dict(tile_taxels=tile, order=order))
+    ref = _independent_tiles(sc, tile)
+    got = list(zip(w["inst"].tolist(), w["k0"].tolist(), w["count"].tolist()))
+    assert got == ref  # bit-exact, instance-major numbering
+    assert sorted(w["order"].tolist()) == list(range(len(ref)))  # a permutation
+    counts = np.diff(sc.tmpl_offset)[sc.inst_tmpl]
+    cover = [np.zeros(c, np.int32) for c in counts]
+    for s in w["order"]:
+        i, k0, c = ref[s]
+        cover[i][k0:k0 + c] += 1
+    assert all(np.all(v == 1) for v in cover)
+
+
+def test_xcd_order_groups_objects():
+    sc = wl.make_c2(n_env=64, res=(8, 10), grid=24)
+    w = api.build_worklist(sc, dict(order=1), xcd_count=8)
+    sdf_of_tile = sc.env_sdf[sc.inst_env[w["inst"]]]
+    slots = w["order"]
+    # slots s with the same s % 8 run on the same XCD: few distinct objects each
+    per_xcd = [len(set(sdf_of_tile[slots[x::8]].tolist())) for x in range(8)]
+    assert max(per_xcd) <= 2, per_xcd
+    # longest-first order is non-increasing in tile size
+    w2 = api.build_worklist(wl.make_uneven_small(), dict(order=2, tile_taxels=256))
+    sizes = w2["count"][w2["order"]]
+    assert np.all(np.diff(sizes) <= 0)
+
+
+def test_bad_tunings_rejected():
+    sc = _uneven()
+    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=7),
+                dict(grid=-1)):
+        with pytest.raises(_abi.TacslError) as ei:
+            api.build_worklist(sc, bad)
+        assert ei.value.code == -3
+    with pytest.raises(_abi.TacslError):
+        api.build_worklist(sc, None, xcd_count=0)

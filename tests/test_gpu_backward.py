@@ -1,0 +1,120 @@
+"""GPU adjoint against the oracle's dual-number gradient and central FD."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2408_06506_amd import workloads as wl  # noqa: E402
+from tests.parity import grad_blocks_close  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"\n[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_06506_amd import api as _api
+    return _api
+
+
+def _gpu_grad(api, plan, sc, wa, wb, delta=None, step=None):
+    st = plan.state(sc.state(step), obj_pose_delta=delta)
+    g = plan.backward(st, torch.as_tensor(wa, device=plan.device), torch.as_tensor(wb, device=plan.device))
+    torch.cuda.synchronize()
+    return np.concatenate([g["g_obj_pose"].cpu().numpy(), g["g_obj_twist"].cpu().numpy(),
+                           g["g_params"].cpu().numpy()], axis=1).astype(np.float64), g
+
+
+@pytest.mark.parametrize("tun", [dict(), dict(tile_taxels=64, schedule=2, grid=3, block=128),
+                                 dict(block=512, tile_taxels=200, order=1, schedule=1, grid=5)])
+def test_adjoint_matches_oracle_small(api, tun):
+    sc = wl.make_small(cfg_id=80, n_env=8)
+    wa, wb = wl.loss_weights(sc.n_taxels, 1)
+    _say(f"adjoint small {tun}")
+    plan = api.Plan(sc, tun)
+    g, _ = _gpu_grad(api, plan, sc, wa, wb)
+    _, ref = oracle.grad(sc, oracle.state64(sc), wa, wb)
+    grad_blocks_close(g, ref, 1e-4, what=f"small {tun}")
+    plan.close()
+
+
+def test_adjoint_at_nonzero_pose_delta(api):
+    sc = wl.make_small(cfg_id=81, n_env=6)
+    rng = np.random.default_rng(5)
+    delta = np.concatenate([rng.uniform(-3e-4, 3e-4, (6, 3)), rng.uniform(-0.05, 0.05, (6, 3))], 1)
+    delta = delta.astype(np.float32)
+    wa, wb = wl.loss_weights(sc.n_taxels, 2)
+    _say("adjoint with delta")
+    plan = api.Plan(sc)
+    g, _ = _gpu_grad(api, plan, sc, wa, wb, delta=delta)
+    _, ref = oracle.grad(sc, oracle.state64(sc, obj_pose_delta=delta), wa, wb)
+    grad_blocks_close(g, ref, 1e-4, what="delta")
+
+
+def test_adjoint_differentiation_workload(api):
+    """1024 envs x 2 pads x 40x50 at 128^3: 32 sampled envs vs dual numbers,
+    and vs FP64 central differences (h = 1e-6) with the kink mask."""
+    sc = wl.make_c5()
+    wa, wb = wl.loss_weights(sc.n_taxels, 5)
+    _say("c5 adjoint")
+    plan = api.Plan(sc)
+    g, _ = _gpu_grad(api, plan, sc, wa, wb)
+    rng = np.random.default_rng(11)
+    sel = np.sort(rng.choice(sc.n_env, 32, replace=False)).astype(np.int32)
+    st = oracle.state64(sc)
+    _, ref = oracle.grad(sc, st, wa, wb, sel_env=sel)
+    grad_blocks_close(g[sel], ref, 1e-4, what="c5 dual")
+    # central FD of the FP64 loss on the same envs, kink-masked on both sides
+    from tests.test_oracle_grad import _perturbed_states
+    pert = _perturbed_states(st, sel)
+    sig0 = oracle.signature(sc, st)
+    keep = np.ones(sc.n_taxels, bool)
+    for pair, _ in pert:
+        for s in pair:
+            keep &= np.all(oracle.signature(sc, s) == sig0, axis=1)
+    mask = keep.astype(np.uint8)
+    wam = (wa * keep).astype(np.float32)
+    wbm = (wb * keep).astype(np.float32)
+    gm, _ = _gpu_grad(api, plan, sc, wam, wbm)
+    fd = np.zeros((sel.size, 16))
+    for d, (pair, step) in enumerate(pert):
+        fd[:, d] = (oracle.loss(sc, pair[0], wa, wb, sel_env=sel, mask=mask)
+                    - oracle.loss(sc, pair[1], wa, wb, sel_env=sel, mask=mask)) / (2 * step)
+    grad_blocks_close(gm[sel], fd, 1e-4, what="c5 FD")
+
+
+def test_autograd_function(api):
+    sc = wl.make_small(cfg_id=82, n_env=4)
+    plan = api.Plan(sc)
+    st = plan.state(sc.state())
+    delta = torch.zeros(sc.n_env, 6, device=plan.device, requires_grad=True)
+    twist = st["obj_twist"].clone().requires_grad_(True)
+    params = st["params"].clone().requires_grad_(True)
+    _say("autograd")
+    depth, normal, fn, ft, wrench = api.force_field(plan, st["pad_pose"], st["obj_pose"], st["pad_twist"],
+                                                    twist, params, delta)
+    wa, wb = wl.loss_weights(sc.n_taxels, 4)
+    wa_t = torch.as_tensor(wa, device=plan.device)
+    wb_t = torch.as_tensor(wb, device=plan.device)
+    loss = (fn * wa_t).sum() + (ft * wb_t).sum()
+    loss.backward()
+    _, ref = oracle.grad(sc, oracle.state64(sc), wa, wb)
+    g = np.concatenate([delta.grad.cpu().numpy(), twist.grad.cpu().numpy(), params.grad.cpu().numpy()], 1)
+    grad_blocks_close(g.astype(np.float64), ref, 1e-4, what="autograd")
+    assert not depth.requires_grad and not wrench.requires_grad and not normal.requires_grad
+
+
+def test_adjoint_deterministic(api):
+    sc = wl.make_small(cfg_id=83, n_env=4)
+    plan = api.Plan(sc, dict(tile_taxels=64, schedule=2, grid=3))
+    wa, wb = wl.loss_weights(sc.n_taxels, 6)
+    _say("adjoint determinism")
+    a, _ = _gpu_grad(api, plan, sc, wa, wb)
+    b, _ = _gpu_grad(api, plan, sc, wa, wb)
+    assert np.array_equal(a, b)
