@@ -57,7 +57,10 @@ def run_main(args, torch, api, wl, autotune):
     st = plan.state(sc.state())
     out = plan.new_outputs()
     tun = None
-    if not args.no_tune:
+    if args.tuning:
+        tun = json.loads(args.tuning)
+        plan.set_tuning(tun)
+    elif not args.no_tune:
         t1 = time.time()
         res = autotune.autotune(plan, sc, st, out, reps=5, tag="c3")
         tun = res["tuning"]
@@ -197,7 +200,15 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--threads", type=int, default=16)
+    ap.add_argument("--tuning", type=str, default=None,
+                    help='fixed tuning as JSON, e.g. {"block":256,"tile_taxels":512,"schedule":2,"grid":1024,"order":1}')
+    ap.add_argument("--only-main", action="store_true", help="roofline workload only (for profiling)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied by a plain device copy before the run (counter scale reference)")
     args = ap.parse_args()
+    if args.only_main:
+        args.no_batched = True
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (environments shard "
               f"across GPUs without exchange; only the single-GPU shard is built here).", file=sys.stderr)
@@ -209,6 +220,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 4} bytes read, {n * 4} bytes written")
+        del src, dst
     m = run_main(args, torch, api, wl, autotune)
     sc = m["scene"]
     traffic = None

@@ -62,7 +62,7 @@ typedef enum {
   TACSL_ERR_RANGE = -3,        /* an id or value out of range (bad index, spacing <= 0, non-finite) */
   TACSL_ERR_HIP = -4,          /* a HIP runtime call failed */
   TACSL_ERR_ALLOC = -5,        /* device or host allocation failed (plan creation only) */
-  TACSL_ERR_UNSUPPORTED = -6,  /* valid but beyond this build's limits (grid > 2^28 nodes, ...) */
+  TACSL_ERR_UNSUPPORTED = -6,  /* valid but beyond this build's limits (grid copy >= 4 GiB, ...) */
   TACSL_ERR_STATE = -7         /* call not valid for this object (e.g. graph of a destroyed plan) */
 } tacsl_status;
 
@@ -79,7 +79,8 @@ typedef enum {
  *   tmpl_offset host [n_tmpl+1] prefix sums of template sizes; [0] = 0, non-decreasing
  *   tmpl_xyz  device [3][T_tmpl] FP32 SoA taxel positions in the pad frame
  *             (T_tmpl = tmpl_offset[n_tmpl]); the pad plane faces +z towards the object
- *   sdf_dims  host [n_sdf][3]  nodes per axis (nx, ny, nz), each >= 2, product <= 2^28 - 1
+ *   sdf_dims  host [n_sdf][3]  nodes per axis (nx, ny, nz), each >= 2; the plan's copy
+ *             (16 bytes per node, x rounded up to even) must stay below 4 GiB, i.e. up to ~645^3
  *   sdf_origin host [n_sdf][3] position of node (0,0,0) in the object frame
  *   sdf_spacing host [n_sdf]   isotropic node spacing h > 0
  *   sdf_offset host [n_sdf]    element offset of each grid in sdf_data
@@ -107,7 +108,8 @@ typedef struct {
  *                stride over the tile list; 2: persistent, dynamic queue
  *   grid         persistent workgroups for schedules 1-2 (0 -> 8 per CU)
  *   order        0: instance-major; 1: XCD-aware (tiles of one object grid
- *                kept on one XCD's L2); 2: longest tiles first */
+ *                kept on one XCD's L2); 2: longest tiles first; 3: object-major
+ *                (the whole GPU on one object grid at a time) */
 typedef struct {
   int32_t block, tile_taxels, schedule, grid, order;
 } tacsl_tuning;
@@ -197,8 +199,9 @@ int tacsl_build_worklist(const tacsl_scene_desc* desc, const tacsl_tuning* tunin
 
 /* Create a plan on the current HIP device: validates the scene, builds the
  * instance offsets and work list, and prepares the SDF pool (node values plus
- * central-difference gradient channels, one-sided on grid faces).  Allocates
- * device memory and synchronizes; not for use inside graph capture.
+ * central-difference gradients, one-sided on grid faces, re-laid out for the
+ * gathers).  Allocates device memory and synchronizes; not for use inside
+ * graph capture.
  * tuning may be NULL (defaults).  On error *out is NULL. */
 int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, tacsl_plan* out);
 

@@ -6,29 +6,43 @@
 
 namespace tacsl {
 
+// Prepared grid ("x-pair columns"): one float4 record per node,
+// (phi, G_x, G_y, G_z) with G the nodal finite-difference gradient (central
+// inside, one-sided on the faces).  Node (i, j, k) is stored at byte
+//   (i >> 1) * stride_q + j * stride_y + k * 32 + (i & 1) * 16,
+//   stride_y = 32 nz,  stride_q = stride_y ny,
+// so one 128-byte line holds 2 x-nodes by 4 z-nodes at one y: the eight
+// corners of a cell are reached from 2 per-lane offsets (x and x+1), with the
+// y step as a scalar offset and the z step as an immediate offset.
+inline int64_t prepared_grid_bytes(int64_t nx, int64_t ny, int64_t nz) {
+  return ((nx + 1) / 2) * ny * nz * 32;
+}
+
 // Static per-pad record, built at plan creation (device, read-only).
 struct InstStatic {
-  const float4* grid;   // prepared nodes (phi, dphi/dx, dphi/dy, dphi/dz) of the pad's object
+  const float4* grid;   // prepared grid of the pad's object (layout above)
   int64_t tmpl_off;     // first taxel of the pad's template within the template rows
   int64_t out_off;      // global taxel index of the pad's first taxel
   int32_t nx, ny, nz;   // grid nodes per axis
   int32_t env;          // environment of the pad
   int32_t count;        // taxels on the pad
   uint32_t grid_bytes;  // bytes of the prepared grid (< 2^32)
+  uint32_t stride_y;    // bytes between consecutive y
+  uint32_t stride_q;    // bytes between consecutive x-pairs
   float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
 };
 
 // Per-step per-pad record written by the prologue (FP64 math, FP32 store).
-//   grid coordinates of a taxel:  u = A x_p + b
-//   pad-frame normal:             n = R^T n_o   (R = object-from-pad rotation)
+//   grid coordinates of a taxel:  u = A x_p + b,  A = R / h  (R = object-from-pad rotation)
+//   pad-frame normal:             n = R^T n_o = h A^T n_o
 //   pad-frame relative velocity:  x_dot = V + W x x_p
 struct InstXf {
   float A[9];
   float b[3];
-  float R[9];
   float V[3];
   float W[3];
   float prm[4];  // k_n, k_d, k_t, mu
+  float h;       // node spacing
   uint32_t ok;   // 0 when the pad's inputs were rejected (then A = 0, b = -1)
 };
 

@@ -8,7 +8,7 @@
 //
 // Kernels
 //   k_prepare_grid  once per plan: node value + nodal finite-difference
-//                   gradient channels as one float4 per node.
+//                   gradient as one float4 record per node, in x-pair columns.
 //   k_prologue      per pad, FP64: relative pose and twist, folded into an
 //                   affine map taxel -> grid coordinates (FP32 record).
 //   k_force_fwd     per tile of taxels: the whole per-taxel path, SoA stores,
@@ -19,10 +19,14 @@
 //
 // Design notes (gfx950): wave64, one taxel per lane per iteration; template
 // positions and outputs are SoA so every load/store instruction moves 256
-// contiguous bytes per wave; the eight float4 corner nodes of a taxel's cell
-// are gathered through a bounds-checked buffer resource (an out-of-range
-// offset reads zeros instead of faulting); per-pad constants live in scalar
-// registers; reductions are fixed-order (deterministic, no float atomics).
+// contiguous bytes per wave; each of the eight corners of a taxel's cell is
+// one 16-byte record (value and gradient), so a taxel costs eight gather
+// instructions (fewer, wider gathers are what the vector L1 handles best);
+// records are laid out so a 128-byte line holds a 2 x 4 patch of nodes (a
+// third fewer lines per taxel than x-fastest rows) and are fetched through a
+// bounds-checked buffer resource (an out-of-range offset reads zeros instead
+// of faulting); per-pad constants live in scalar registers; reductions are
+// fixed-order (deterministic, no float atomics).
 #include <hip/hip_runtime.h>
 
 #include "tacsl_internal.h"
@@ -36,11 +40,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float4* p, uin
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(p), (short)0, (int)bytes, kBufferFlags);
 }
 
-__device__ __forceinline__ float4 load_node(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+// One node record: per-lane byte offset + uniform (scalar) byte offset.
+__device__ __forceinline__ float4 load_node(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Element k of a row whose base is uniform; k * 4 < 2^32 (tiles hold < 2^30 taxels).
+__device__ __forceinline__ float at(const float* base, uint32_t k) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (k << 2));
+}
+__device__ __forceinline__ void put(float* base, uint32_t k, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (k << 2)) = v;
+}
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -56,7 +69,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ---------------------------------------------------------------------------
 // SDF preparation: (phi, G) per node, G = nodal finite differences (central
-// inside, one-sided on the faces).  Counts non-finite node values.
+// inside, one-sided on the faces), stored in the x-pair column layout.
+// Counts non-finite node values.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_prepare_grid(const float* __restrict__ phi, float4* __restrict__ out,
                                                       int nx, int ny, int nz, float h,
@@ -78,7 +92,8 @@ __global__ __launch_bounds__(256) void k_prepare_grid(const float* __restrict__ 
     const float gz = (phi[((int64_t)kh * ny + j) * nx + i] - phi[((int64_t)kl * ny + j) * nx + i]) /
                      ((float)(kh - kl) * h);
     if (!isfinite(p)) atomicAdd(bad, 1u);
-    out[idx] = make_float4(p, gx, gy, gz);
+    const int64_t rec = ((int64_t)(i >> 1) * ny + j) * nz * 2 + (int64_t)k * 2 + (i & 1);
+    out[rec] = make_float4(p, gx, gy, gz);
   }
 }
 
@@ -176,10 +191,8 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
                            Ro[2] * d[0] + Ro[5] * d[1] + Ro[8] * d[2]};
     const double h = st.h;
     const double org[3] = {st.ox, st.oy, st.oz};
-    for (int k = 0; k < 9; ++k) {
-      x.A[k] = (float)(R[k] / h);
-      x.R[k] = (float)R[k];
-    }
+    for (int k = 0; k < 9; ++k) x.A[k] = (float)(R[k] / h);
+    x.h = st.h;
     for (int r = 0; r < 3; ++r) x.b[r] = (float)((top[r] - org[r]) / h);
     const double wo[3] = {ot[3], ot[4], ot[5]};
     const double dv[3] = {pt[0] - ot[0] - (wo[1] * d[2] - wo[2] * d[1]), pt[1] - ot[1] - (wo[2] * d[0] - wo[0] * d[2]),
@@ -192,7 +205,8 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     for (int k = 0; k < 4; ++k) x.prm[k] = pr[k];
     x.ok = 1;
   } else {
-    for (int k = 0; k < 9; ++k) { x.A[k] = 0.f; x.R[k] = 0.f; }
+    for (int k = 0; k < 9; ++k) x.A[k] = 0.f;
+    x.h = 0.f;
     for (int k = 0; k < 3; ++k) { x.b[k] = -1.f; x.V[k] = 0.f; x.W[k] = 0.f; }
     for (int k = 0; k < 4; ++k) x.prm[k] = 0.f;
     x.ok = 0;
@@ -209,7 +223,7 @@ struct TaxelFwd {
   bool force;    // contact and |g|^2 >= 1e-12
   float ux, uy, uz;
   float tx, ty, tz;
-  float4 c[8];   // corner nodes, index dx + 2 dy + 4 dz
+  float4 c[8];   // corner records (phi, G), index dx + 2 dy + 4 dz
   float phi;
   float gx, gy, gz, r;
   float nox, noy, noz;
@@ -244,17 +258,20 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   f.tx = f.ux - (float)cx;
   f.ty = f.uy - (float)cy;
   f.tz = f.uz - (float)cz;
-  const uint32_t sy = 16u * (uint32_t)st.nx;
-  const uint32_t sz = sy * (uint32_t)st.ny;
-  const uint32_t o = 16u * (uint32_t)((cz * st.ny + cy) * st.nx + cx);
-  f.c[0] = load_node(rs, o);
-  f.c[1] = load_node(rs, o + 16u);
-  f.c[2] = load_node(rs, o + sy);
-  f.c[3] = load_node(rs, o + sy + 16u);
-  f.c[4] = load_node(rs, o + sz);
-  f.c[5] = load_node(rs, o + sz + 16u);
-  f.c[6] = load_node(rs, o + sz + sy);
-  f.c[7] = load_node(rs, o + sz + sy + 16u);
+  // per-lane offsets of the two x-nodes; y steps are scalar, z steps immediate
+  const uint32_t yz = (uint32_t)cy * st.stride_y + (uint32_t)cz * 32u;
+  const uint32_t x0 = (uint32_t)cx, x1 = x0 + 1u;
+  const uint32_t o0 = (x0 >> 1) * st.stride_q + (x0 & 1u) * 16u + yz;
+  const uint32_t o1 = (x1 >> 1) * st.stride_q + (x1 & 1u) * 16u + yz;
+  const uint32_t sy = st.stride_y;
+  f.c[0] = load_node(rs, o0, 0u);
+  f.c[1] = load_node(rs, o1, 0u);
+  f.c[2] = load_node(rs, o0, sy);
+  f.c[3] = load_node(rs, o1, sy);
+  f.c[4] = load_node(rs, o0 + 32u, 0u);
+  f.c[5] = load_node(rs, o1 + 32u, 0u);
+  f.c[6] = load_node(rs, o0 + 32u, sy);
+  f.c[7] = load_node(rs, o1 + 32u, sy);
   const float4* c = f.c;
   f.phi = tri(c[0].x, c[1].x, c[2].x, c[3].x, c[4].x, c[5].x, c[6].x, c[7].x, f.tx, f.ty, f.tz);
   if (!(f.phi < 0.f)) return;
@@ -269,10 +286,11 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   f.nox = f.gx * f.r;
   f.noy = f.gy * f.r;
   f.noz = f.gz * f.r;
-  // pad-frame normal n = R^T n_o
-  f.n[0] = fmaf(x.R[0], f.nox, fmaf(x.R[3], f.noy, x.R[6] * f.noz));
-  f.n[1] = fmaf(x.R[1], f.nox, fmaf(x.R[4], f.noy, x.R[7] * f.noz));
-  f.n[2] = fmaf(x.R[2], f.nox, fmaf(x.R[5], f.noy, x.R[8] * f.noz));
+  // pad-frame normal n = R^T n_o = h A^T n_o
+  const float hx = x.h;
+  f.n[0] = hx * fmaf(x.A[0], f.nox, fmaf(x.A[3], f.noy, x.A[6] * f.noz));
+  f.n[1] = hx * fmaf(x.A[1], f.nox, fmaf(x.A[4], f.noy, x.A[7] * f.noz));
+  f.n[2] = hx * fmaf(x.A[2], f.nox, fmaf(x.A[5], f.noy, x.A[8] * f.noz));
   // relative velocity x_dot = V + W x p
   f.v[0] = x.V[0] + fmaf(x.W[1], pz, -x.W[2] * py);
   f.v[1] = x.V[1] + fmaf(x.W[2], px, -x.W[0] * pz);
@@ -305,37 +323,45 @@ __device__ __forceinline__ int next_slot(int slot, int dynamic, int32_t* queue, 
 // ---------------------------------------------------------------------------
 // Forward kernel.
 // ---------------------------------------------------------------------------
+// Tile records are read at a workgroup-uniform index through restrict
+// (read-only, non-aliased) pointers, so they land in scalar registers and the
+// buffer resource of the grid is uniform (no per-lane waterfall).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_force_fwd(FwdArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_force_fwd(
+    const Tile* __restrict__ tiles, const int32_t* __restrict__ order, int32_t n_tiles, int32_t dynamic,
+    int32_t* __restrict__ queue, const InstStatic* __restrict__ stat, const InstXf* __restrict__ xfs,
+    const float* __restrict__ tmpl, int64_t tmpl_T, float* __restrict__ depth, float* __restrict__ normal,
+    float* __restrict__ fn, float* __restrict__ ft, int64_t T, float* __restrict__ partial) {
   constexpr int NW = BLOCK / 64;
   __shared__ float red[NW][6];
   __shared__ int s_next;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int slot = blockIdx.x;
-  while (slot < a.n_tiles) {
-    const int tid = a.order[slot];
-    const Tile tl = a.tiles[tid];
-    const InstStatic st = a.stat[tl.inst];
-    const InstXf x = a.xf[tl.inst];
+  while (slot < n_tiles) {
+    const int tid = __builtin_amdgcn_readfirstlane(order[slot]);
+    const Tile tl = tiles[tid];
+    const InstStatic st = stat[tl.inst];
+    const InstXf x = xfs[tl.inst];
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
-    const float* tx = a.tmpl + st.tmpl_off + tl.k0;
-    const float* ty = tx + a.tmpl_T;
-    const float* tz = ty + a.tmpl_T;
+    const float* tx = tmpl + st.tmpl_off + tl.k0;
+    const float* ty = tx + tmpl_T;
+    const float* tz = ty + tmpl_T;
     const int64_t ob = st.out_off + tl.k0;
-    float* o_d = a.depth + ob;
-    float* o_n0 = a.normal + ob;
-    float* o_n1 = o_n0 + a.T;
-    float* o_n2 = o_n1 + a.T;
-    float* o_f0 = a.fn + ob;
-    float* o_f1 = o_f0 + a.T;
-    float* o_f2 = o_f1 + a.T;
-    float* o_t0 = a.ft + ob;
-    float* o_t1 = o_t0 + a.T;
-    float* o_t2 = o_t1 + a.T;
+    float* o_d = depth + ob;
+    float* o_n0 = normal + ob;
+    float* o_n1 = o_n0 + T;
+    float* o_n2 = o_n1 + T;
+    float* o_f0 = fn + ob;
+    float* o_f1 = o_f0 + T;
+    float* o_f2 = o_f1 + T;
+    float* o_t0 = ft + ob;
+    float* o_t1 = o_t0 + T;
+    float* o_t2 = o_t1 + T;
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
-      const float px = tx[k], py = ty[k], pz = tz[k];
+    for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK) {
+      // uniform 64-bit base + 32-bit lane offset: saddr addressing, no 64-bit VALU math
+      const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
       TaxelFwd f;
       taxel_forward(x, st, rs, px, py, pz, f);
       float dep = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
@@ -346,10 +372,10 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(FwdArgs a) {
         fn0 = f.fn[0]; fn1 = f.fn[1]; fn2 = f.fn[2];
         ft0 = f.ft[0]; ft1 = f.ft[1]; ft2 = f.ft[2];
       }
-      o_d[k] = dep;
-      o_n0[k] = n0; o_n1[k] = n1; o_n2[k] = n2;
-      o_f0[k] = fn0; o_f1[k] = fn1; o_f2[k] = fn2;
-      o_t0[k] = ft0; o_t1[k] = ft1; o_t2[k] = ft2;
+      put(o_d, k, dep);
+      put(o_n0, k, n0); put(o_n1, k, n1); put(o_n2, k, n2);
+      put(o_f0, k, fn0); put(o_f1, k, fn1); put(o_f2, k, fn2);
+      put(o_t0, k, ft0); put(o_t1, k, ft1); put(o_t2, k, ft2);
       const float F0 = fn0 + ft0, F1 = fn1 + ft1, F2 = fn2 + ft2;
       acc[0] += F0;
       acc[1] += F1;
@@ -368,9 +394,9 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(FwdArgs a) {
       float s = 0.f;
 #pragma unroll
       for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
-      a.partial[6 * (int64_t)tid + threadIdx.x] = s;
+      partial[6 * (int64_t)tid + threadIdx.x] = s;
     }
-    slot = next_slot<BLOCK>(slot, a.dynamic, a.queue, &s_next);
+    slot = next_slot<BLOCK>(slot, dynamic, queue, &s_next);
   }
 }
 
@@ -391,40 +417,44 @@ __global__ __launch_bounds__(256) void k_wrench_reduce(WrenchReduceArgs a) {
 //   and the four parameter adjoints.  k_grad_reduce maps them to the world.
 // ---------------------------------------------------------------------------
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_force_bwd(BwdArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_force_bwd(
+    const Tile* __restrict__ tiles, const int32_t* __restrict__ order, int32_t n_tiles, int32_t dynamic,
+    int32_t* __restrict__ queue, const InstStatic* __restrict__ stat, const InstXf* __restrict__ xfs,
+    const float* __restrict__ tmpl, int64_t tmpl_T, const float* __restrict__ w_fn,
+    const float* __restrict__ w_ft, int64_t T, double* __restrict__ partial) {
   constexpr int NW = BLOCK / 64;
   __shared__ double red[NW][kBwdAcc];
   __shared__ int s_next;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int slot = blockIdx.x;
-  while (slot < a.n_tiles) {
-    const int tid = a.order[slot];
-    const Tile tl = a.tiles[tid];
-    const InstStatic st = a.stat[tl.inst];
-    const InstXf x = a.xf[tl.inst];
+  while (slot < n_tiles) {
+    const int tid = __builtin_amdgcn_readfirstlane(order[slot]);
+    const Tile tl = tiles[tid];
+    const InstStatic st = stat[tl.inst];
+    const InstXf x = xfs[tl.inst];
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
-    const float* tx = a.tmpl + st.tmpl_off + tl.k0;
-    const float* ty = tx + a.tmpl_T;
-    const float* tz = ty + a.tmpl_T;
+    const float* tx = tmpl + st.tmpl_off + tl.k0;
+    const float* ty = tx + tmpl_T;
+    const float* tz = ty + tmpl_T;
     const int64_t ob = st.out_off + tl.k0;
-    const float* wa0 = a.w_fn + ob;
-    const float* wa1 = wa0 + a.T;
-    const float* wa2 = wa1 + a.T;
-    const float* wb0 = a.w_ft + ob;
-    const float* wb1 = wb0 + a.T;
-    const float* wb2 = wb1 + a.T;
+    const float* wa0 = w_fn + ob;
+    const float* wa1 = wa0 + T;
+    const float* wa2 = wa1 + T;
+    const float* wb0 = w_ft + ob;
+    const float* wb1 = wb0 + T;
+    const float* wb2 = wb1 + T;
     const float kn = x.prm[0], kd = x.prm[1], kt = x.prm[2], mu = x.prm[3];
     float acc[kBwdAcc];
 #pragma unroll
     for (int c = 0; c < kBwdAcc; ++c) acc[c] = 0.f;
-    for (int k = threadIdx.x; k < tl.count; k += BLOCK) {
-      const float px = tx[k], py = ty[k], pz = tz[k];
+    for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK) {
+      const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
       TaxelFwd f;
       taxel_forward(x, st, rs, px, py, pz, f);
       if (!f.force) continue;
-      const float A[3] = {wa0[k], wa1[k], wa2[k]};
-      const float B[3] = {wb0[k], wb1[k], wb2[k]};
+      const float A[3] = {at(wa0, k), at(wa1, k), at(wa2, k)};
+      const float B[3] = {at(wb0, k), at(wb1, k), at(wb2, k)};
       // f_n = s n
       float nb[3], vb[3], vtb[3];
       for (int c = 0; c < 3; ++c) nb[c] = f.s * A[c];
@@ -468,10 +498,10 @@ __global__ __launch_bounds__(BLOCK) void k_force_bwd(BwdArgs a) {
       acc[6] += f.n[1] * nb[2] - f.n[2] * nb[1];
       acc[7] += f.n[2] * nb[0] - f.n[0] * nb[2];
       acc[8] += f.n[0] * nb[1] - f.n[1] * nb[0];
-      // n = R^T n_o  ->  n_o_bar = R n_bar
-      const float nob0 = x.R[0] * nb[0] + x.R[1] * nb[1] + x.R[2] * nb[2];
-      const float nob1 = x.R[3] * nb[0] + x.R[4] * nb[1] + x.R[5] * nb[2];
-      const float nob2 = x.R[6] * nb[0] + x.R[7] * nb[1] + x.R[8] * nb[2];
+      // n = R^T n_o  ->  n_o_bar = R n_bar = h A n_bar
+      const float nob0 = x.h * (x.A[0] * nb[0] + x.A[1] * nb[1] + x.A[2] * nb[2]);
+      const float nob1 = x.h * (x.A[3] * nb[0] + x.A[4] * nb[1] + x.A[5] * nb[2]);
+      const float nob2 = x.h * (x.A[6] * nb[0] + x.A[7] * nb[1] + x.A[8] * nb[2]);
       // n_o = g / |g|
       const float pr = nob0 * f.nox + nob1 * f.noy + nob2 * f.noz;
       const float gb0 = f.r * (nob0 - pr * f.nox);
@@ -501,9 +531,9 @@ __global__ __launch_bounds__(BLOCK) void k_force_bwd(BwdArgs a) {
       double s = 0.0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
-      a.partial[kBwdAcc * (int64_t)tid + threadIdx.x] = s;
+      partial[kBwdAcc * (int64_t)tid + threadIdx.x] = s;
     }
-    slot = next_slot<BLOCK>(slot, a.dynamic, a.queue, &s_next);
+    slot = next_slot<BLOCK>(slot, dynamic, queue, &s_next);
   }
 }
 
@@ -614,12 +644,16 @@ hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+#define TACSL_FWD_ARGS                                                                                  \
+  a.tiles, a.order, a.n_tiles, a.dynamic, a.queue, a.stat, a.xf, a.tmpl, a.tmpl_T, a.depth, a.normal, a.fn, \
+      a.ft, a.T, a.partial
+
 hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream) {
   switch (block) {
-    case 64: hipLaunchKernelGGL(k_force_fwd<64>, dim3(grid), dim3(64), 0, stream, a); break;
-    case 128: hipLaunchKernelGGL(k_force_fwd<128>, dim3(grid), dim3(128), 0, stream, a); break;
-    case 256: hipLaunchKernelGGL(k_force_fwd<256>, dim3(grid), dim3(256), 0, stream, a); break;
-    case 512: hipLaunchKernelGGL(k_force_fwd<512>, dim3(grid), dim3(512), 0, stream, a); break;
+    case 64: hipLaunchKernelGGL(k_force_fwd<64>, dim3(grid), dim3(64), 0, stream, TACSL_FWD_ARGS); break;
+    case 128: hipLaunchKernelGGL(k_force_fwd<128>, dim3(grid), dim3(128), 0, stream, TACSL_FWD_ARGS); break;
+    case 256: hipLaunchKernelGGL(k_force_fwd<256>, dim3(grid), dim3(256), 0, stream, TACSL_FWD_ARGS); break;
+    case 512: hipLaunchKernelGGL(k_force_fwd<512>, dim3(grid), dim3(512), 0, stream, TACSL_FWD_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -632,12 +666,15 @@ hipError_t launch_wrench_reduce(const WrenchReduceArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+#define TACSL_BWD_ARGS \
+  a.tiles, a.order, a.n_tiles, a.dynamic, a.queue, a.stat, a.xf, a.tmpl, a.tmpl_T, a.w_fn, a.w_ft, a.T, a.partial
+
 hipError_t launch_backward(const BwdArgs& a, int block, int grid, hipStream_t stream) {
   switch (block) {
-    case 64: hipLaunchKernelGGL(k_force_bwd<64>, dim3(grid), dim3(64), 0, stream, a); break;
-    case 128: hipLaunchKernelGGL(k_force_bwd<128>, dim3(grid), dim3(128), 0, stream, a); break;
-    case 256: hipLaunchKernelGGL(k_force_bwd<256>, dim3(grid), dim3(256), 0, stream, a); break;
-    case 512: hipLaunchKernelGGL(k_force_bwd<512>, dim3(grid), dim3(512), 0, stream, a); break;
+    case 64: hipLaunchKernelGGL(k_force_bwd<64>, dim3(grid), dim3(64), 0, stream, TACSL_BWD_ARGS); break;
+    case 128: hipLaunchKernelGGL(k_force_bwd<128>, dim3(grid), dim3(128), 0, stream, TACSL_BWD_ARGS); break;
+    case 256: hipLaunchKernelGGL(k_force_bwd<256>, dim3(grid), dim3(256), 0, stream, TACSL_BWD_ARGS); break;
+    case 512: hipLaunchKernelGGL(k_force_bwd<512>, dim3(grid), dim3(512), 0, stream, TACSL_BWD_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

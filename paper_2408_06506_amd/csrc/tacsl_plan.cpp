@@ -17,7 +17,7 @@ using tacsl::Tile;
 
 namespace {
 
-constexpr int64_t kMaxGridNodes = (int64_t(1) << 28) - 1;  // 16 B per prepared node, offsets < 2^32
+constexpr int64_t kMaxGridBytes = (int64_t(1) << 32) - 1;  // prepared grid addressed with 32-bit offsets
 constexpr int64_t kMaxTemplate = int64_t(1) << 30;
 constexpr int kXcdCount = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin across them
 
@@ -53,8 +53,7 @@ int validate(const tacsl_scene_desc* d) {
   for (int g = 0; g < d->n_sdf; ++g) {
     const int32_t* n = d->sdf_dims + 3 * g;
     if (n[0] < 2 || n[1] < 2 || n[2] < 2) return TACSL_ERR_SHAPE;
-    const int64_t nodes = (int64_t)n[0] * n[1] * n[2];
-    if (nodes > kMaxGridNodes) return TACSL_ERR_UNSUPPORTED;
+    if (tacsl::prepared_grid_bytes(n[0], n[1], n[2]) > kMaxGridBytes) return TACSL_ERR_UNSUPPORTED;
     const float h = d->sdf_spacing[g];
     if (!(h > 0.f) || !std::isfinite(h)) return TACSL_ERR_RANGE;
     for (int a = 0; a < 3; ++a)
@@ -77,7 +76,7 @@ int resolve_tuning(const tacsl_tuning* in, int cu_count, tacsl_tuning* out) {
   if (t.tile_taxels < 0 || (t.tile_taxels > 0 && t.tile_taxels < 64) || t.tile_taxels > kMaxTemplate)
     return TACSL_ERR_RANGE;
   if (t.schedule < 0 || t.schedule > 2) return TACSL_ERR_RANGE;
-  if (t.order < 0 || t.order > 2) return TACSL_ERR_RANGE;
+  if (t.order < 0 || t.order > 3) return TACSL_ERR_RANGE;
   if (t.grid < 0) return TACSL_ERR_RANGE;
   if (t.grid == 0) t.grid = std::max(1, cu_count) * 8;
   *out = t;
@@ -110,6 +109,11 @@ int make_worklist(const tacsl_scene_desc& d, const tacsl_tuning& t, int xcd, std
   auto cost = [&](int32_t tid) { return (int64_t)std::max(tiles[tid].count, 1); };
   if (t.order == 2) {
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+  } else if (t.order == 3) {
+    // object-major: all XCDs work on one object grid at a time
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return d.env_sdf[d.inst_env[tiles[a].inst]] < d.env_sdf[d.inst_env[tiles[b].inst]];
+    });
   } else if (t.order == 1 && n > 0) {
     // group by object grid, cut into xcd contiguous segments of equal cost,
     // interleave so that slot s runs on XCD s % xcd while segments last
@@ -409,10 +413,11 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   for (int i = 0; i < d.n_inst; ++i) p->inst_off[i + 1] = p->inst_off[i] + tmpl_count(d, i);
   p->T = p->inst_off[d.n_inst];
 
-  // prepared SDF pool: (phi, grad) float4 per node
+  // prepared SDF pool: (phi, G) float4 records in x-pair columns
   std::vector<int64_t> gbase((size_t)d.n_sdf + 1, 0);
   for (int g = 0; g < d.n_sdf; ++g)
-    gbase[g + 1] = gbase[g] + (int64_t)d.sdf_dims[3 * g] * d.sdf_dims[3 * g + 1] * d.sdf_dims[3 * g + 2];
+    gbase[g + 1] = gbase[g] + tacsl::prepared_grid_bytes(d.sdf_dims[3 * g], d.sdf_dims[3 * g + 1],
+                                                         d.sdf_dims[3 * g + 2]) / (int64_t)sizeof(float4);
   p->grids_bytes = gbase[d.n_sdf] * (int64_t)sizeof(float4);
   if (dalloc(&p->grids, (size_t)gbase[d.n_sdf]) != hipSuccess) return fail(TACSL_ERR_ALLOC);
   uint32_t* d_bad = nullptr;
@@ -449,6 +454,8 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     s.env = d.inst_env[i];
     s.count = (int32_t)tmpl_count(d, i);
     s.grid_bytes = (uint32_t)((gbase[g + 1] - gbase[g]) * (int64_t)sizeof(float4));
+    s.stride_y = 32u * (uint32_t)s.nz;
+    s.stride_q = s.stride_y * (uint32_t)s.ny;
     s.ox = d.sdf_origin[3 * g];
     s.oy = d.sdf_origin[3 * g + 1];
     s.oz = d.sdf_origin[3 * g + 2];

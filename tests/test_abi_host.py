@@ -100,11 +100,16 @@ def test_invalid_descriptions_return_codes():
     so = sc.sdf_offset.copy()
     so[0] = -5
     assert api.validate_scene(_mut(sc, sdf_offset=so)) == -3
-    # grid too large for 32-bit buffer offsets (2^28 nodes of 16 B)
+    # the plan's grid copy (16 B per node, x rounded up to even) must stay below 4 GiB
+    def copy_bytes(n):
+        n = [int(v) for v in n]
+        return ((n[0] + 1) // 2) * n[1] * n[2] * 32
     dims = sc.sdf_dims.copy()
-    dims[0] = (1024, 1024, 256)
+    dims[0] = (646, 646, 646)
+    assert copy_bytes(dims[0]) >= 2 ** 32
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == -6
-    dims[0] = (1024, 1024, 255)
+    dims[0] = (644, 645, 645)
+    assert copy_bytes(dims[0]) < 2 ** 32
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == 0
     # counts
     assert api.validate_scene(_mut(sc, n_env=-1)) == -2
@@ -133,7 +138,7 @@ def _independent_tiles(sc, tile):
 
 
 @pytest.mark.parametrize("tile", [0, 64, 100, 1024])
-@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_worklist_covers_every_taxel_once(tile, order):
     sc = _uneven()
     w = api.build_worklist(sc, dict(tile_taxels=tile, order=order))
@@ -165,7 +170,7 @@ def test_xcd_order_groups_objects():
 
 def test_bad_tunings_rejected():
     sc = _uneven()
-    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=7),
+    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=4),
                 dict(grid=-1)):
         with pytest.raises(_abi.TacslError) as ei:
             api.build_worklist(sc, bad)

@@ -129,7 +129,7 @@ def test_roofline_shape_sampled(api):
     g = gpu_outputs_np(out, rows=torch.as_tensor(rows))
     g["wrench"] = out["wrench"][torch.as_tensor(sel, dtype=torch.long)].cpu().numpy().astype(np.float64)
     ref = oracle.force_field(sc, oracle.state64(sc), sel=sel)
-    compare(sc, g, ref, D=2e-3, kn=KN, sel=sel, what="c3")
+    compare(sc, g, ref, D=2e-3, kn=KN, sel=sel, what="c3")  # stricter than the 4 mm cap
     # properties that hold at any size, on every taxel
     d = out["depth"]
     assert torch.all(d >= 0)
@@ -139,7 +139,7 @@ def test_roofline_shape_sampled(api):
     assert torch.all(ftm <= 0.8 * fnm * (1 + 1e-5) + 1e-6)
     frac = (d > 0).float().mean().item()
     print(f"c3 realized contact fraction {frac:.4f}")
-    assert 0.6 < frac < 0.75
+    assert 0.62 < frac < 0.75
 
 
 def test_nonfinite_pose_sets_status_and_zero_pad(api):
