@@ -85,8 +85,10 @@ typedef enum {
  *   sdf_spacing host [n_sdf]   isotropic node spacing h > 0
  *   sdf_offset host [n_sdf]    element offset of each grid in sdf_data
  *   sdf_data  device           node values (FP32 metres), x fastest: (k*ny + j)*nx + i
- * The plan copies what it needs: tmpl_xyz must stay valid for the plan's
- * lifetime; sdf_data is only read at plan creation. */
+ * The plan copies what it needs: tmpl_xyz and sdf_data are only read at plan
+ * creation.  Taxels are visited in template order, 64 consecutive ones per
+ * wavefront: numbering a template in compact blocks (e.g. 8 x 8 tiles of a
+ * grid) keeps each wavefront's SDF gathers on few cache lines. */
 typedef struct {
   int32_t n_env, n_inst, n_tmpl, n_sdf;
   const int32_t* inst_env;

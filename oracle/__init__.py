@@ -57,7 +57,7 @@ def _load():
         P = ctypes.c_void_p
         lib.oracle_offsets.argtypes = [P, P]
         lib.oracle_force_field.argtypes = [P, P, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int]
-        lib.oracle_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, P, ctypes.c_int]
+        lib.oracle_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int]
         lib.oracle_loss.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int]
         lib.oracle_signature.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_footprint.argtypes = [P, P, ctypes.c_int, P]
@@ -133,10 +133,12 @@ def force_field(scene, state, sel=None, nthreads=0, signature=False):
     return out
 
 
-def grad(scene, state, wa, wb, sel_env=None, mask=None, nthreads=0):
+def grad(scene, state, wa, wb, sel_env=None, mask=None, nthreads=0, with_abs=False):
     """Loss per selected env and its 16-direction gradient (dual numbers).
 
-    Columns: dt(3), dtheta(3), v_o(3), w_o(3), k_n, k_d, k_t, mu.
+    Columns: dt(3), dtheta(3), v_o(3), w_o(3), k_n, k_d, k_t, mu.  With
+    ``with_abs`` also returns, per env and column, the sum over taxels of the
+    absolute per-taxel contributions (the scale of a cancelling sum).
     """
     if sel_env is None:
         sel_env = np.arange(scene.n_env, dtype=np.int32)
@@ -147,8 +149,11 @@ def grad(scene, state, wa, wb, sel_env=None, mask=None, nthreads=0):
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     loss = np.zeros(sel_env.size)
     g = np.zeros((sel_env.size, 16))
+    gabs = np.zeros((sel_env.size, 16)) if with_abs else None
     _load().oracle_grad(ctypes.byref(b.sc), ctypes.byref(b.st), _ptr(wa), _ptr(wb), _ptr(m),
-                        int(sel_env.size), _ptr(sel_env), _ptr(loss), _ptr(g), int(nthreads))
+                        int(sel_env.size), _ptr(sel_env), _ptr(loss), _ptr(g), _ptr(gabs), int(nthreads))
+    if with_abs:
+        return loss, g, gabs
     return loss, g
 
 

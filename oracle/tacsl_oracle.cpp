@@ -383,10 +383,13 @@ int oracle_force_field(const oracle_scene* sc, const oracle_state* st, int n_sel
 // R_o <- Exp(dtheta) R_o, t_o <- t_o + dt, world frame, at the state's
 // obj_pose_delta), object twist (v[3], w[3], world), params (k_n,k_d,k_t,mu).
 // Weights wa/wb are [3][T] indexed by the global taxel index; mask (may be
-// NULL) zeroes a taxel's contribution when 0.
+// NULL) zeroes a taxel's contribution when 0.  gabs (may be NULL) receives,
+// per environment and direction, the sum over taxels of the absolute value
+// of each taxel's contribution to the gradient (the scale of a sum that
+// cancels).
 int oracle_grad(const oracle_scene* sc, const oracle_state* st, const double* wa, const double* wb,
                 const uint8_t* mask, int n_sel_env, const int32_t* sel_env, double* loss, double* grad,
-                int nthreads) {
+                double* gabs, int nthreads) {
   typedef Dual<16> D;
   std::vector<int64_t> off(sc->n_inst + 1);
   oracle_offsets(sc, off.data());
@@ -399,6 +402,7 @@ int oracle_grad(const oracle_scene* sc, const oracle_state* st, const double* wa
   for (int s = 0; s < n_sel_env; ++s) {
     int e = sel_env[s];
     D acc(0.0);
+    double aabs[16] = {0};
     for (int i : env_inst[e]) {
       V3<D> dt, dth;
       D* comps[6] = {&dt.x, &dt.y, &dt.z, &dth.x, &dth.y, &dth.z};
@@ -416,10 +420,13 @@ int oracle_grad(const oracle_scene* sc, const oracle_state* st, const double* wa
         D l = o.fn.x * wa[j] + o.fn.y * wa[T + j] + o.fn.z * wa[2 * T + j] +
               o.ft.x * wb[j] + o.ft.y * wb[T + j] + o.ft.z * wb[2 * T + j];
         acc = acc + l;
+        for (int a = 0; a < 16; ++a) aabs[a] += std::fabs(l.d[a]);
       }
     }
     loss[s] = acc.v;
     for (int a = 0; a < 16; ++a) grad[16 * s + a] = acc.d[a];
+    if (gabs)
+      for (int a = 0; a < 16; ++a) gabs[16 * s + a] = aabs[a];
   }
   return 0;
 }

@@ -104,9 +104,8 @@ class Plan:
     ``scene`` is any object with the host arrays of a scene description
     (inst_env, inst_tmpl, env_sdf, tmpl_offset, tmpl_xyz, sdf_dims,
     sdf_origin, sdf_spacing, sdf_offset, sdf_data, n_env, n_inst), e.g.
-    ``workloads.Scene``.  The template positions are kept on the device for
-    the plan's lifetime; the SDF node values are only needed while the plan
-    is created (the plan keeps its own prepared copy).
+    ``workloads.Scene``.  Template positions and SDF node values are only
+    needed while the plan is created (the plan keeps its own copies).
     """
 
     def __init__(self, scene, tun=None, device="cuda"):
@@ -115,9 +114,9 @@ class Plan:
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self._plan = ctypes.c_void_p(None)
-        self.tmpl = torch.as_tensor(_np(scene.tmpl_xyz, np.float32).reshape(3, -1), device=self.device)
+        tmpl = torch.as_tensor(_np(scene.tmpl_xyz, np.float32).reshape(3, -1), device=self.device)
         sdf = torch.as_tensor(_np(scene.sdf_data, np.float32).reshape(-1), device=self.device)
-        self._hs = _HostScene(scene, self.tmpl.data_ptr() if self.tmpl.numel() else None,
+        self._hs = _HostScene(scene, tmpl.data_ptr() if tmpl.numel() else None,
                               sdf.data_ptr() if sdf.numel() else None)
         t = _tuning_obj(tun)
         with torch.cuda.device(self.device):
@@ -125,7 +124,7 @@ class Plan:
             _abi.check(self._lib.tacsl_plan_create(ctypes.byref(self._hs.desc),
                                                    ctypes.byref(t) if t is not None else None,
                                                    ctypes.byref(self._plan)), "tacsl_plan_create")
-        del sdf
+        del sdf, tmpl
         self.n_env = self._hs.n_env
         self.n_inst = self._hs.n_inst
         info = self.info()

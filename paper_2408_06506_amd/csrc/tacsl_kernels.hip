@@ -282,7 +282,7 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   const float gg = fmaf(f.gx, f.gx, fmaf(f.gy, f.gy, f.gz * f.gz));
   if (!(gg >= 1e-12f)) return;
   f.force = true;
-  f.r = rsqrtf(gg);
+  f.r = __builtin_amdgcn_rsqf(gg);  // hardware reciprocal square root (~1 ulp)
   f.nox = f.gx * f.r;
   f.noy = f.gy * f.r;
   f.noz = f.gz * f.r;
@@ -301,10 +301,11 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
     f.fn[a] = f.s * f.n[a];
     f.vt[a] = fmaf(-f.dd, f.n[a], f.v[a]);
   }
-  f.vtn = sqrtf(fmaf(f.vt[0], f.vt[0], fmaf(f.vt[1], f.vt[1], f.vt[2] * f.vt[2])));
+  // hardware square root and reciprocal (~1 ulp each); slipping implies |v_t| > 0
+  f.vtn = __builtin_amdgcn_sqrtf(fmaf(f.vt[0], f.vt[0], fmaf(f.vt[1], f.vt[1], f.vt[2] * f.vt[2])));
   f.cap = x.prm[3] * fabsf(f.s);
   f.stick = x.prm[2] * f.vtn <= f.cap;
-  const float coef = f.stick ? -x.prm[2] : -(f.cap / f.vtn);
+  const float coef = f.stick ? -x.prm[2] : -f.cap * __builtin_amdgcn_rcpf(f.vtn);
   for (int a = 0; a < 3; ++a) f.ft[a] = coef * f.vt[a];
 }
 

@@ -170,8 +170,9 @@ struct tacsl_plan_s {
   // scene copies needed to rebuild the work list
   std::vector<int32_t> inst_env, inst_tmpl, env_sdf;
   std::vector<int64_t> tmpl_offset;
-  const float* tmpl_xyz = nullptr;
+  const float* tmpl_xyz = nullptr;  // plan-owned copy of the templates
   int64_t tmpl_T = 0;
+  float* d_tmpl = nullptr;  // plan-owned copy of the templates
   // device buffers
   float4* grids = nullptr;
   int64_t grids_bytes = 0;
@@ -225,6 +226,7 @@ struct tacsl_plan_s {
   void free_all() {
     free_timer();
     free_worklist();
+    dfree(d_tmpl);
     dfree(grids);
     dfree(d_stat);
     dfree(d_xf);
@@ -407,8 +409,17 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   p->inst_tmpl.assign(d.inst_tmpl, d.inst_tmpl + d.n_inst);
   p->env_sdf.assign(d.env_sdf, d.env_sdf + d.n_env);
   p->tmpl_offset.assign(d.tmpl_offset, d.tmpl_offset + (d.n_tmpl > 0 ? d.n_tmpl + 1 : 0));
-  p->tmpl_xyz = d.tmpl_xyz;
   p->tmpl_T = d.n_tmpl > 0 ? d.tmpl_offset[d.n_tmpl] : 0;
+  // plan-owned copy of the templates (taxels are visited in the caller's
+  // order, so a compact numbering -- e.g. 8 x 8 blocks -- gives compact waves)
+  {
+    const int64_t TT = p->tmpl_T;
+    if (dalloc(&p->d_tmpl, (size_t)(3 * TT)) != hipSuccess) return fail(TACSL_ERR_ALLOC);
+    if (TT > 0 && hipMemcpy(p->d_tmpl, d.tmpl_xyz, (size_t)(3 * TT) * sizeof(float), hipMemcpyDeviceToDevice) !=
+                      hipSuccess)
+      return fail(TACSL_ERR_HIP);
+    p->tmpl_xyz = p->d_tmpl;
+  }
   p->inst_off.assign((size_t)d.n_inst + 1, 0);
   for (int i = 0; i < d.n_inst; ++i) p->inst_off[i + 1] = p->inst_off[i] + tmpl_count(d, i);
   p->T = p->inst_off[d.n_inst];
@@ -484,6 +495,7 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   rc = install_worklist(p, t);
   if (rc != TACSL_OK) return fail(rc);
   p->ws_bytes = (int64_t)(st.size() * sizeof(InstStatic) + (size_t)d.n_inst * sizeof(InstXf) +
+                          (size_t)p->tmpl_T * 16 +
                           (size_t)p->n_tiles * (sizeof(Tile) + sizeof(int32_t) + 6 * sizeof(float) +
                                                 tacsl::kBwdAcc * sizeof(double)) +
                           ((size_t)d.n_inst + 1) * sizeof(int64_t) + eib.size() * 4 + ei.size() * 4 + 4);

@@ -21,7 +21,8 @@ Conventions
 * Twists are ``vx vy vz wx wy wz``: linear velocity of the body origin and
   angular velocity, both in the world frame.
 * Pad templates are SoA ``[3][K]``; the pad is the plane z = 0 with +z pointing
-  towards the object.  Taxel k = j * nx + i.
+  towards the object.  Taxels are numbered in 8 x 8 tiles of the grid
+  (``taxel_grid_index`` maps a template index to its row and column).
 * SDF grids are node-centred, isotropic spacing h, x fastest; node (i,j,k) sits
   at ``origin + h * (i, j, k)`` in the object frame; values are negative
   inside the object.
@@ -220,18 +221,36 @@ PAD_W = 20 * MM
 PAD_H = 25 * MM
 
 
+TAXEL_BLOCK = 8
+
+
+def taxel_grid_index(nx: int, ny: int, block: int = TAXEL_BLOCK) -> np.ndarray:
+    """Template numbering of an nx x ny taxel grid: (j, i) of every template
+    index, in block x block tiles (tiles row-major, taxels row-major within a
+    tile).  64 consecutive taxels then form a compact 8 x 8 patch."""
+    ij = []
+    for jb in range(0, ny, block):
+        for ib in range(0, nx, block):
+            for j in range(jb, min(jb + block, ny)):
+                for i in range(ib, min(ib + block, nx)):
+                    ij.append((j, i))
+    return np.asarray(ij, dtype=np.int64).reshape(-1, 2)
+
+
 @functools.lru_cache(maxsize=32)
-def pad_template(nx: int, ny: int, width: float = PAD_W, height: float = PAD_H):
-    """Planar pad of nx x ny taxels at cell centres, SoA float32 [3][nx*ny]."""
+def pad_template(nx: int, ny: int, width: float = PAD_W, height: float = PAD_H, block: int = TAXEL_BLOCK):
+    """Planar pad of nx x ny taxels at cell centres, SoA float32 [3][nx*ny].
+
+    Taxels are numbered in block x block tiles (``taxel_grid_index``); use
+    ``block=max(nx, ny)`` for plain row-major numbering.
+    """
     px = width / nx
     py = height / ny
-    i = np.arange(nx, dtype=np.float64)
-    j = np.arange(ny, dtype=np.float64)
-    jj, ii = np.meshgrid(j, i, indexing="ij")
-    x = -0.5 * width + (ii + 0.5) * px
-    y = -0.5 * height + (jj + 0.5) * py
+    ji = taxel_grid_index(nx, ny, block)
+    x = -0.5 * width + (ji[:, 1] + 0.5) * px
+    y = -0.5 * height + (ji[:, 0] + 0.5) * py
     z = np.zeros_like(x)
-    t = np.stack([x.reshape(-1), y.reshape(-1), z.reshape(-1)]).astype(np.float32)
+    t = np.stack([x, y, z]).astype(np.float32)
     t.setflags(write=False)
     return t
 

@@ -137,11 +137,11 @@ def _independent_tiles(sc, tile):
     return out
 
 
-@pytest.mark.parametrize("tile", [0, 64, 100, 1024])
+@pytest.mark.parametrize("tile", [0, 64, 192, 1024])
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
 def test_worklist_covers_every_taxel_once(tile, order):
     sc = _uneven()
-    w = api.build_worklist(sc, dict(tile_taxels=tile, order=order))
+    w = api.build_worklist(sc, dict(block=64, tile_taxels=tile, order=order))
     ref = _independent_tiles(sc, tile)
     got = list(zip(w["inst"].tolist(), w["k0"].tolist(), w["count"].tolist()))
     assert got == ref  # bit-exact, instance-major numbering
@@ -163,7 +163,7 @@ def test_xcd_order_groups_objects():
     per_xcd = [len(set(sdf_of_tile[slots[x::8]].tolist())) for x in range(8)]
     assert max(per_xcd) <= 2, per_xcd
     # longest-first order is non-increasing in tile size
-    w2 = api.build_worklist(wl.make_uneven_small(), dict(order=2, tile_taxels=256))
+    w2 = api.build_worklist(wl.make_uneven_small(), dict(order=2, tile_taxels=256))  # block 256
     sizes = w2["count"][w2["order"]]
     assert np.all(np.diff(sizes) <= 0)
 

@@ -31,16 +31,16 @@ def _gpu_grad(api, plan, sc, wa, wb, delta=None, step=None):
                            g["g_params"].cpu().numpy()], axis=1).astype(np.float64), g
 
 
-@pytest.mark.parametrize("tun", [dict(), dict(tile_taxels=64, schedule=2, grid=3, block=128),
-                                 dict(block=512, tile_taxels=200, order=1, schedule=1, grid=5)])
+@pytest.mark.parametrize("tun", [dict(), dict(tile_taxels=64, schedule=2, grid=3, block=64),
+                                 dict(block=512, tile_taxels=1024, order=1, schedule=1, grid=5)])
 def test_adjoint_matches_oracle_small(api, tun):
     sc = wl.make_small(cfg_id=80, n_env=8)
     wa, wb = wl.loss_weights(sc.n_taxels, 1)
     _say(f"adjoint small {tun}")
     plan = api.Plan(sc, tun)
     g, _ = _gpu_grad(api, plan, sc, wa, wb)
-    _, ref = oracle.grad(sc, oracle.state64(sc), wa, wb)
-    grad_blocks_close(g, ref, 1e-4, what=f"small {tun}")
+    _, ref, gabs = oracle.grad(sc, oracle.state64(sc), wa, wb, with_abs=True)
+    grad_blocks_close(g, ref, 1e-4, what=f"small {tun}", g_abs=gabs)
     plan.close()
 
 
@@ -53,8 +53,8 @@ def test_adjoint_at_nonzero_pose_delta(api):
     _say("adjoint with delta")
     plan = api.Plan(sc)
     g, _ = _gpu_grad(api, plan, sc, wa, wb, delta=delta)
-    _, ref = oracle.grad(sc, oracle.state64(sc, obj_pose_delta=delta), wa, wb)
-    grad_blocks_close(g, ref, 1e-4, what="delta")
+    _, ref, gabs = oracle.grad(sc, oracle.state64(sc, obj_pose_delta=delta), wa, wb, with_abs=True)
+    grad_blocks_close(g, ref, 1e-4, what="delta", g_abs=gabs)
 
 
 def test_adjoint_differentiation_workload(api):
@@ -68,8 +68,8 @@ def test_adjoint_differentiation_workload(api):
     rng = np.random.default_rng(11)
     sel = np.sort(rng.choice(sc.n_env, 32, replace=False)).astype(np.int32)
     st = oracle.state64(sc)
-    _, ref = oracle.grad(sc, st, wa, wb, sel_env=sel)
-    grad_blocks_close(g[sel], ref, 1e-4, what="c5 dual")
+    _, ref, gabs = oracle.grad(sc, st, wa, wb, sel_env=sel, with_abs=True)
+    grad_blocks_close(g[sel], ref, 1e-4, what="c5 dual", g_abs=gabs)
     # central FD of the FP64 loss on the same envs, kink-masked on both sides
     from tests.test_oracle_grad import _perturbed_states
     pert = _perturbed_states(st, sel)
@@ -86,7 +86,8 @@ def test_adjoint_differentiation_workload(api):
     for d, (pair, step) in enumerate(pert):
         fd[:, d] = (oracle.loss(sc, pair[0], wa, wb, sel_env=sel, mask=mask)
                     - oracle.loss(sc, pair[1], wa, wb, sel_env=sel, mask=mask)) / (2 * step)
-    grad_blocks_close(gm[sel], fd, 1e-4, what="c5 FD")
+    _, _, gabs_m = oracle.grad(sc, st, wa, wb, sel_env=sel, mask=mask, with_abs=True)
+    grad_blocks_close(gm[sel], fd, 1e-4, what="c5 FD", g_abs=gabs_m)
 
 
 def test_autograd_function(api):
@@ -104,15 +105,15 @@ def test_autograd_function(api):
     wb_t = torch.as_tensor(wb, device=plan.device)
     loss = (fn * wa_t).sum() + (ft * wb_t).sum()
     loss.backward()
-    _, ref = oracle.grad(sc, oracle.state64(sc), wa, wb)
+    _, ref, gabs = oracle.grad(sc, oracle.state64(sc), wa, wb, with_abs=True)
     g = np.concatenate([delta.grad.cpu().numpy(), twist.grad.cpu().numpy(), params.grad.cpu().numpy()], 1)
-    grad_blocks_close(g.astype(np.float64), ref, 1e-4, what="autograd")
+    grad_blocks_close(g.astype(np.float64), ref, 1e-4, what="autograd", g_abs=gabs)
     assert not depth.requires_grad and not wrench.requires_grad and not normal.requires_grad
 
 
 def test_adjoint_deterministic(api):
     sc = wl.make_small(cfg_id=83, n_env=4)
-    plan = api.Plan(sc, dict(tile_taxels=64, schedule=2, grid=3))
+    plan = api.Plan(sc, dict(block=64, tile_taxels=64, schedule=2, grid=3))
     wa, wb = wl.loss_weights(sc.n_taxels, 6)
     _say("adjoint determinism")
     a, _ = _gpu_grad(api, plan, sc, wa, wb)

@@ -52,10 +52,10 @@ def test_tiny_ball_100_steps(api):
 TUNINGS = [
     dict(),
     dict(block=64),
-    dict(block=128, tile_taxels=64),
-    dict(block=512, tile_taxels=300, order=2),
-    dict(block=256, tile_taxels=128, schedule=1, grid=7, order=1),
-    dict(block=256, tile_taxels=256, schedule=2, grid=5),
+    dict(block=64, tile_taxels=64),
+    dict(block=512, tile_taxels=512, order=2),
+    dict(block=128, tile_taxels=128, schedule=1, grid=7, order=1),
+    dict(block=256, tile_taxels=256, schedule=2, grid=5, order=3),
     dict(block=128, schedule=2, grid=3, order=1),
 ]
 
@@ -81,7 +81,8 @@ def test_small_scenes_all_tunings(api, seed):
 
 def test_uneven_batch(api):
     sc = wl.make_uneven_small(cfg_id=12, n_env=12, substeps=3)
-    for tun in (dict(), dict(tile_taxels=128, schedule=2, order=2), dict(tile_taxels=64, schedule=1, order=1)):
+    for tun in (dict(), dict(block=128, tile_taxels=128, schedule=2, order=2),
+                dict(block=64, tile_taxels=64, schedule=1, order=1)):
         _say(f"uneven tuning {tun}")
         plan = api.Plan(sc, tun)
         for step in range(3):
@@ -95,7 +96,7 @@ def test_uneven_batch(api):
 
 def test_deterministic_run_to_run(api):
     sc = wl.make_small(cfg_id=70, n_env=6)
-    plan = api.Plan(sc, dict(tile_taxels=128, schedule=2, grid=4))
+    plan = api.Plan(sc, dict(block=128, tile_taxels=128, schedule=2, grid=4))
     st = plan.state(sc.state())
     _say("determinism")
     a = {k: v.clone() for k, v in plan.forward(st).items()}

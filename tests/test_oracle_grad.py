@@ -194,3 +194,21 @@ def test_pose_gradient_convention_independent_of_exp():
                     - oracle.loss(sc, p[1], wa, wb, sel_env=sel, mask=mask)) / (2 * h) for p in states], 1)
     num = np.linalg.norm(g[:, :6] - fd, axis=1)
     assert np.all(num <= 1e-5 * np.linalg.norm(g[:, :6], axis=1)), num / np.linalg.norm(g[:, :6], axis=1)
+
+
+def test_abs_sum_scale():
+    """The absolute-sum scale bounds the gradient and equals it for one taxel."""
+    sc = wl.make_small(cfg_id=50, n_env=2)
+    st = oracle.state64(sc)
+    wa, wb = wl.loss_weights(sc.n_taxels, 1)
+    _, g, gabs = oracle.grad(sc, st, wa, wb, with_abs=True)
+    assert np.all(gabs >= np.abs(g) * (1 - 1e-12))
+    o = oracle.force_field(sc, st)
+    j = int(np.flatnonzero(o["depth"] > 0)[3])
+    e = int(sc.inst_env[np.searchsorted(oracle.offsets(sc), j, side="right") - 1])
+    w1a = np.zeros_like(wa)
+    w1b = np.zeros_like(wb)
+    w1a[:, j] = wa[:, j]
+    w1b[:, j] = wb[:, j]
+    _, g1, a1 = oracle.grad(sc, st, w1a, w1b, sel_env=np.array([e]), with_abs=True)
+    np.testing.assert_allclose(a1, np.abs(g1), rtol=1e-15, atol=0)
