@@ -51,8 +51,10 @@ __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t
 __device__ __forceinline__ float at(const float* base, uint32_t k) {
   return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (k << 2));
 }
+// Outputs stream out once per step: non-temporal stores keep them from
+// evicting SDF lines from L2 and the memory-side cache.
 __device__ __forceinline__ void put(float* base, uint32_t k, float v) {
-  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (k << 2)) = v;
+  __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (k << 2)));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
