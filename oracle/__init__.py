@@ -62,6 +62,7 @@ def _load():
         lib.oracle_signature.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_footprint.argtypes = [P, P, ctypes.c_int, P]
         lib.oracle_footprint.restype = ctypes.c_int64
+        lib.oracle_contact_impulse.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double, P, P]
         _lib = lib
     return _lib
 
@@ -193,3 +194,17 @@ def state64(scene, step=None, obj_pose_delta=None):
     if obj_pose_delta is not None:
         st["obj_pose_delta"] = np.asarray(obj_pose_delta, dtype=np.float64)
     return st
+
+
+def contact_impulse(eps, epsdot, inv_mass, env, kc, dt):
+    """Implicit soft-contact impulse per contact (Section III-A); FP64 arrays."""
+    eps = np.ascontiguousarray(eps, np.float64)
+    epsdot = np.ascontiguousarray(epsdot, np.float64)
+    inv_mass = np.ascontiguousarray(inv_mass, np.float64)
+    env = None if env is None else np.ascontiguousarray(env, np.int32)
+    kc = np.ascontiguousarray(kc, np.float64).reshape(-1, 2)
+    lam = np.zeros(eps.size)
+    dv = np.zeros(eps.size)
+    _load().oracle_contact_impulse(int(eps.size), _ptr(eps), _ptr(epsdot), _ptr(inv_mass), _ptr(env), _ptr(kc),
+                                   float(dt), _ptr(lam), _ptr(dv))
+    return lam, dv

@@ -525,3 +525,27 @@ int64_t oracle_footprint(const oracle_scene* sc, const oracle_state* st, int n_s
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Implicit soft-contact impulse (Section III-A, "Constraint Solution").
+// The Kelvin-Voigt contact force is applied as an implicit spring: the
+// impulse over a step satisfies the force law at the END of the step,
+//   lambda = dt max(-kappa eps+ - c epsdot+, 0),
+//   epsdot+ = epsdot + lambda / m,  eps+ = eps + dt epsdot+,
+// whose solution is lambda = max(0, (-dt kappa eps - alpha epsdot) / (1 + alpha/m))
+// with alpha = dt (dt kappa + c).  Per contact, FP64; inv_mass = 1/m (0 for
+// an immovable body); kappa, c per environment.
+// ---------------------------------------------------------------------------
+extern "C" int oracle_contact_impulse(int64_t n, const double* eps, const double* epsdot, const double* inv_mass,
+                                      const int32_t* env, const double* kc, double dt, double* lambda, double* dv) {
+  for (int64_t k = 0; k < n; ++k) {
+    const int e = env ? env[k] : 0;
+    const double kappa = kc[2 * e], c = kc[2 * e + 1];
+    const double alpha = dt * (dt * kappa + c);
+    double l = (-dt * kappa * eps[k] - alpha * epsdot[k]) / (1.0 + alpha * inv_mass[k]);
+    if (!(l > 0.0)) l = 0.0;
+    lambda[k] = l;
+    if (dv) dv[k] = l * inv_mass[k];
+  }
+  return 0;
+}
