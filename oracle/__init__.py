@@ -208,3 +208,37 @@ def contact_impulse(eps, epsdot, inv_mass, env, kc, dt):
     _load().oracle_contact_impulse(int(eps.size), _ptr(eps), _ptr(epsdot), _ptr(inv_mass), _ptr(env), _ptr(kc),
                                    float(dt), _ptr(lam), _ptr(dv))
     return lam, dv
+
+
+def observation(scene, ff, tmpl_bin, n_bins, scale=(1.0, 1.0, 1.0), clip=0.0, sel=None):
+    """Force-field observation per pad (the 14 x 10 x 3 policy input of
+    Section V-B): channels (|f_n|, f_t,x, f_t,y) of the pad-frame forces,
+    averaged over the taxels of each bin, divided by the channel scale and
+    clipped to [-clip, clip] (clip <= 0: no clipping); an empty bin is 0.
+
+    ``ff`` is the output of ``force_field`` for the same ``sel`` (taxel rows
+    instance-major); ``tmpl_bin`` gives the bin of each template taxel (-1:
+    none).  Returns FP64 [n_sel][n_bins][3]."""
+    sel = np.arange(scene.n_inst) if sel is None else np.asarray(sel)
+    tmpl_bin = np.asarray(tmpl_bin)
+    scale = np.asarray(scale, np.float64)
+    obs = np.zeros((sel.size, n_bins, 3))
+    row = 0
+    for s, i in enumerate(sel):
+        p = scene.inst_tmpl[i]
+        a, b = int(scene.tmpl_offset[p]), int(scene.tmpl_offset[p + 1])
+        cnt = b - a
+        bins = tmpl_bin[a:b]
+        fn = ff["fn"][:, row:row + cnt]
+        ft = ff["ft"][:, row:row + cnt]
+        row += cnt
+        ch = np.stack([np.linalg.norm(fn, axis=0), ft[0], ft[1]], axis=1)
+        m = bins >= 0
+        counts = np.bincount(bins[m], minlength=n_bins)
+        for c in range(3):
+            sums = np.bincount(bins[m], weights=ch[m, c], minlength=n_bins)
+            mean = np.divide(sums, counts, out=np.zeros(n_bins), where=counts > 0)
+            obs[s, :, c] = mean / scale[c]
+    if clip > 0:
+        obs = np.clip(obs, -clip, clip)
+    return obs

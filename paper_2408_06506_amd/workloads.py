@@ -811,3 +811,29 @@ def make_contacts(n_env: int, per_env: int, seed: int = 31, dt: float = IMPULSE_
     inv_mass[rng.random(n) < 0.1] = 0.0
     kc = np.stack([rng.uniform(150.0, 350.0, n_env), rng.uniform(0.0, 1.0, n_env)], 1).astype(np.float32)
     return Contacts(eps, eps_dot, inv_mass, env, kc, float(dt))
+
+
+# ---------------------------------------------------------------------------
+# Observation layout: the 14 x 10 x 3 force-field observation per finger of
+# Section V-B.  Bins split the pad's taxel grid into bins_y rows (along the
+# 25 mm pad height) by bins_x columns (along the 20 mm width); a taxel at grid
+# position (j, i) belongs to bin (j * bins_y // ny) * bins_x + (i * bins_x // nx).
+# ---------------------------------------------------------------------------
+OBS_BINS_X = 10
+OBS_BINS_Y = 14
+
+
+def pad_observation_bins(nx: int, ny: int, bins_x: int = OBS_BINS_X, bins_y: int = OBS_BINS_Y,
+                         block: int = TAXEL_BLOCK) -> np.ndarray:
+    """Bin of every template taxel of an nx x ny pad (template numbering)."""
+    ji = taxel_grid_index(nx, ny, block)
+    return ((ji[:, 0] * bins_y // ny) * bins_x + (ji[:, 1] * bins_x // nx)).astype(np.int32)
+
+
+def scene_observation_bins(scene: Scene, bins_x: int = OBS_BINS_X, bins_y: int = OBS_BINS_Y) -> np.ndarray:
+    """Concatenated bin maps of the scene's templates (named "<nx>x<ny>")."""
+    parts = []
+    for name in scene.tmpl_names:
+        nx, ny = (int(v) for v in name.split("x"))
+        parts.append(pad_observation_bins(nx, ny, bins_x, bins_y))
+    return np.concatenate(parts) if parts else np.zeros(0, np.int32)
