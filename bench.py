@@ -14,7 +14,11 @@ Also reported:
 * batched_vs_plain: the uneven batch (4096 envs, pads {20x25, 40x50, 80x100},
   grids {64,128,256}^3 x 8 objects) as one persistent launch per substep vs
   one plain launch per (pad, grid) group, both captured as HIP graphs of 100
-  substeps, with the per-taxel outputs of the two compared.
+  substeps, with the per-taxel outputs of the two compared;
+* differentiation: adjoint throughput on 1024 envs x 2 pads x 40x50;
+* contact_impulse: the batched implicit soft-contact impulse at the contact
+  count of the roofline batch (16384 pads x 64 contacts) and as a 33.5 M
+  contact stream, against HBM bandwidth.
 """
 from __future__ import annotations
 
@@ -38,15 +42,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(scene):
-    """Compulsory bytes of one step: 40 B/taxel of outputs written once, the
-    template read once, per-pad pose/twist in and wrench out, per-env pose,
-    twist and parameters in."""
+FOOTPRINT = os.path.join(ROOT, "tests", "golden", "sdf_footprint.json")
+
+
+def sdf_footprint_nodes(key, scene):
+    """Distinct scalar SDF nodes touched by one step's taxel stencils, as
+    counted once for the seeded workload and stored with the test fixtures."""
+    with open(FOOTPRINT) as f:
+        rec = json.load(f)["workloads"][key]
+    if rec["n_taxels"] != scene.n_taxels or rec["n_inst"] != scene.n_inst:
+        raise RuntimeError(f"stored SDF footprint of {key} does not describe this scene")
+    return int(rec["nodes"])
+
+
+def algorithmic_bytes(scene, footprint_nodes):
+    """Compulsory bytes of one step: 40 B/taxel of outputs written once, 4 B
+    per distinct scalar SDF node the stencils touch, the template read once,
+    per-pad pose/twist in and wrench out, per-env pose, twist and parameters
+    in."""
     T = scene.n_taxels
     tmpl = 12 * int(scene.tmpl_offset[-1])
     per_inst = (7 + 6 + 6) * 4
     per_env = (7 + 6 + 4) * 4
-    return 40 * T + tmpl + per_inst * scene.n_inst + per_env * scene.n_env
+    return 40 * T + 4 * footprint_nodes + tmpl + per_inst * scene.n_inst + per_env * scene.n_env
 
 
 def run_main(args, torch, api, wl, autotune):
@@ -81,13 +99,15 @@ def run_main(args, torch, api, wl, autotune):
     plan.timer_start(0)
     ms_step = wall * 1e3 / args.steps
     value = sc.n_taxels * args.steps / wall
-    B = algorithmic_bytes(sc)
+    V = sdf_footprint_nodes("roofline_8192x2x80x100_256", sc)
+    B = algorithmic_bytes(sc, V)
     k_avg = float(np.mean(kms))
     achieved = B / (k_avg * 1e-3)
     contact = float((out["depth"] > 0).float().mean().item())
     log(f"{ms_step:.4f} ms/step, kernel {k_avg:.4f} ms, {achieved / 1e9:.1f} GB/s, contact {contact:.3f}")
-    return dict(scene=sc, plan=plan, state=st, out=out, tuning=tun or plan.tuning, ms_step=ms_step,
-                value=value, kernel_ms=k_avg, kernel_ms_all=kms, bytes=B, achieved=achieved, contact=contact)
+    return dict(scene=sc, plan=plan, state=st, out=out, tuning=plan.tuning(), ms_step=ms_step,
+                value=value, kernel_ms=k_avg, kernel_ms_all=kms, bytes=B, footprint=V, achieved=achieved,
+                contact=contact)
 
 
 def run_cpu_baseline(sc, budget_threads):
@@ -190,6 +210,125 @@ def run_batched_vs_plain(args, torch, api, wl, autotune):
     return res
 
 
+def run_backward(args, torch, api, wl):
+    """Adjoint throughput on the differentiation workload (1024 envs x 2 pads
+    x 40x50, 128^3): per step the forward prologue is recomputed, then the
+    adjoint kernel (recomputation + reverse mode) and the per-env reduction.
+    Algorithmic bytes: 24 B/taxel of upstream weights read once, 4 B per
+    distinct scalar SDF node touched, the template, state and 64 B/env of
+    gradients."""
+    sc = wl.make_c5()
+    plan = api.Plan(sc)
+    st = plan.state(sc.state())
+    st["obj_pose_delta"] = torch.zeros(sc.n_env, 6, device=plan.device)
+    wa, wb = wl.loss_weights(sc.n_taxels, 5)
+    wa_t = torch.as_tensor(wa, device=plan.device)
+    wb_t = torch.as_tensor(wb, device=plan.device)
+    g = plan.backward(st, wa_t, wb_t)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        plan.backward(st, wa_t, wb_t, g)
+    steps = max(10, args.steps)
+    plan.timer_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.backward(st, wa_t, wb_t, g)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = plan.timer_read(steps)
+    plan.close()
+    V = sdf_footprint_nodes("differentiation_1024x2x40x50_128", sc)
+    B = (24 * sc.n_taxels + 4 * V + 12 * int(sc.tmpl_offset[-1]) + (7 + 6) * 4 * sc.n_inst
+         + (7 + 6 + 4 + 6) * 4 * sc.n_env + 64 * sc.n_env)
+    k_avg = float(np.mean(kms))
+    log(f"backward: {wall * 1e3 / steps:.4f} ms/step, kernel {k_avg:.4f} ms")
+    return {"workload": "differentiation: 1024 envs x 2 pads x 40x50 taxels, 5 objects at 128^3",
+            "taxels": sc.n_taxels, "ms_per_step": wall * 1e3 / steps,
+            "taxel_evals_per_s": sc.n_taxels * steps / wall, "kernel": "k_force_bwd",
+            "kernel_avg_ms": k_avg, "algorithmic_bytes_per_launch": B,
+            "achieved_GBps": B / (k_avg * 1e-3) / 1e9, "frac_of_hbm_peak": B / (k_avg * 1e-3) / HBM_PEAK}
+
+
+def run_observation(args, torch, api, wl, sc, tun):
+    """Fused observation epilogue on the roofline batch (14 x 10 bins x 3
+    channels per pad): observation only (no per-taxel stores) and observation
+    with the per-taxel fields, same tuning as the main leg.  Algorithmic bytes
+    of the observation-only pass: the stencil footprint, the template and bin
+    map, state in, wrench and observation out."""
+    plan = api.Plan(sc, tun)
+    bins = wl.scene_observation_bins(sc)
+    plan.set_observation(bins, 140, scale=(1.0, 1.0, 1.0))
+    st = plan.state(sc.state())
+    obs = plan.new_observation()
+    out_o = dict(wrench=torch.empty(sc.n_inst, 6, device=plan.device))
+    res = {}
+    for label, out in (("observation_only", out_o), ("observation_and_fields", plan.new_outputs())):
+        for _ in range(args.warmup):
+            plan.observe(st, obs=obs, out=out)
+        steps = max(10, args.steps)
+        plan.timer_start(steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.observe(st, obs=obs, out=out)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = float(np.mean(plan.timer_read(steps)))
+        plan.timer_start(0)
+        res[label] = {"ms_per_step": wall * 1e3 / steps, "kernel_avg_ms": kms,
+                      "taxel_evals_per_s": sc.n_taxels * steps / wall}
+        log(f"observation {label}: {wall * 1e3 / steps:.4f} ms/step, kernel {kms:.4f} ms")
+        del out
+    V = sdf_footprint_nodes("roofline_8192x2x80x100_256", sc)
+    B = (4 * V + 16 * int(sc.tmpl_offset[-1]) + (7 + 6) * 4 * sc.n_inst + (7 + 6 + 4) * 4 * sc.n_env
+         + (6 + 140 * 3) * 4 * sc.n_inst)
+    k = res["observation_only"]["kernel_avg_ms"]
+    res["observation_only"].update({"algorithmic_bytes_per_launch": B, "achieved_GBps": B / (k * 1e-3) / 1e9})
+    res["workload"] = "roofline batch, 14 x 10 x 3 observation per pad (channels |f_n|, f_t,x, f_t,y)"
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_impulse(args, torch, api, wl):
+    """Batched implicit soft-contact impulse: per call 16 B read (eps, eps_dot,
+    1/m, env) and 8 B written (lambda, dv) per contact, plus 8 B per
+    environment of (kappa, c).  Each call is bracketed by its own event pair on
+    the stream it is launched on."""
+    res = {}
+    for label, n_env, per_env in (("pads of the roofline batch x 64 contacts", 16384, 64),
+                                  ("33.5 M contact stream", 262144, 128)):
+        c = wl.make_contacts(n_env=n_env, per_env=per_env, seed=11)
+        f = lambda a: torch.as_tensor(a, device="cuda")
+        eps, ed, im, env, kc = f(c.eps), f(c.eps_dot), f(c.inv_mass), f(c.env), f(c.kc)
+        lam = torch.empty_like(eps)
+        dv = torch.empty_like(eps)
+        for _ in range(5):
+            api.contact_impulse(eps, ed, im, kc, c.dt, env=env, lam=lam, dv=dv)
+        reps = max(20, args.steps)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            api.contact_impulse(eps, ed, im, kc, c.dt, env=env, lam=lam, dv=dv)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        B = 24 * c.n + 8 * n_env
+        res["scene" if n_env == 16384 else "stream"] = {
+            "workload": label, "contacts": c.n, "kernel": "k_contact_impulse_x4", "kernel_avg_ms": ms,
+            "contacts_per_s": c.n / (ms * 1e-3), "wall_ms_per_call": wall * 1e3 / reps,
+            "algorithmic_bytes_per_launch": B, "achieved_GBps": B / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": B / (ms * 1e-3) / HBM_PEAK}
+        log(f"impulse {label}: {c.n} contacts, {ms * 1e3:.2f} us, {B / (ms * 1e-3) / 1e9:.0f} GB/s")
+        del eps, ed, im, env, kc, lam, dv
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +337,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-impulse", action="store_true")
+    ap.add_argument("--no-observation", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--threads", type=int, default=16)
     ap.add_argument("--tuning", type=str, default=None,
@@ -209,6 +351,9 @@ def main():
     if args.only_main:
         args.no_batched = True
         args.no_cpu_baseline = True
+        args.no_backward = True
+        args.no_impulse = True
+        args.no_observation = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (environments shard "
               f"across GPUs without exchange; only the single-GPU shard is built here).", file=sys.stderr)
@@ -232,16 +377,25 @@ def main():
     m = run_main(args, torch, api, wl, autotune)
     sc = m["scene"]
     traffic = None
+    observation = None
+    if not args.no_observation:
+        observation = run_observation(args, torch, api, wl, sc, m["tuning"])
     roof = {"bound": "hbm", "achieved": m["achieved"] / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": m["achieved"] / HBM_PEAK, "traffic": traffic, "kernel": "k_force_fwd",
             "kernel_avg_ms": m["kernel_ms"], "algorithmic_bytes_per_launch": m["bytes"],
-            "bytes_per_taxel": m["bytes"] / sc.n_taxels}
+            "bytes_per_taxel": m["bytes"] / sc.n_taxels, "sdf_footprint_nodes": m["footprint"]}
     m["plan"].close()
     del m["out"]
     torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         batched = run_batched_vs_plain(args, torch, api, wl, autotune)
+    backward = None
+    if not args.no_backward:
+        backward = run_backward(args, torch, api, wl)
+    impulse = None
+    if not args.no_impulse:
+        impulse = run_impulse(args, torch, api, wl)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -255,7 +409,8 @@ def main():
                                "8 analytic objects voxelized at 256^3 FP32, ~70% of taxels in contact",
                    "n_env": sc.n_env, "n_pads": sc.n_inst, "taxels_per_step": sc.n_taxels,
                    "contact_fraction": m["contact"], "tuning": m["tuning"], "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched,
+        "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched, "differentiation": backward,
+        "contact_impulse": impulse, "observation": observation,
     }
     print(json.dumps(line), flush=True)
 

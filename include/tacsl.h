@@ -69,6 +69,7 @@ typedef enum {
 /* Bits OR-ed into tacsl_outputs.status / tacsl_grads.status by the kernels. */
 #define TACSL_DEV_NONFINITE_POSE 0x1u /* a pose, twist or parameter is NaN/Inf: that pad outputs zeros */
 #define TACSL_DEV_ZERO_QUAT 0x2u      /* a quaternion has zero norm: that pad outputs zeros */
+#define TACSL_DEV_BAD_CONTACT 0x4u    /* tacsl_contact_impulse: an invalid contact (see there) got lambda = 0 */
 
 /* Scene: everything that stays fixed across steps.  Read at plan creation.
  *   n_env   environments (>= 0); n_inst pads (instances, >= 0);
@@ -80,7 +81,8 @@ typedef enum {
  *   tmpl_xyz  device [3][T_tmpl] FP32 SoA taxel positions in the pad frame
  *             (T_tmpl = tmpl_offset[n_tmpl]); the pad plane faces +z towards the object
  *   sdf_dims  host [n_sdf][3]  nodes per axis (nx, ny, nz), each >= 2; the plan's copy
- *             (16 bytes per node, x rounded up to even) must stay below 4 GiB, i.e. up to ~645^3
+ *             (16 bytes per node, x rounded up to even) must stay below 4 GiB, i.e. up to ~645^3,
+ *             and 32 ny nz below 2^24 (ny nz < 524288, e.g. 724 x 724); else TACSL_ERR_UNSUPPORTED
  *   sdf_origin host [n_sdf][3] position of node (0,0,0) in the object frame
  *   sdf_spacing host [n_sdf]   isotropic node spacing h > 0
  *   sdf_offset host [n_sdf]    element offset of each grid in sdf_data
@@ -220,6 +222,30 @@ int tacsl_plan_offsets(tacsl_plan plan, int64_t* host_inst_offset);
  * pointers except obj_pose_delta and status are required when n_inst > 0. */
 int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, hipStream_t stream);
 
+/* Force-field observation (the policy input of Section V-B: per finger a
+ * small grid of bins with three channels).  For every pad and bin the
+ * channels (|f_n|, f_t,x, f_t,y), pad frame, are averaged over the pad's
+ * taxels in that bin, divided by scale[c] and clipped to [-clip, clip]
+ * (clip <= 0: no clipping); a bin without taxels reads 0.
+ *   n_bins    bins per pad, 1..TACSL_MAX_OBS_BINS (e.g. 14 x 10 = 140); 0 removes the observation
+ *   tmpl_bin  host int32 [T_tmpl]: bin of each template taxel, -1 = in no bin
+ *   scale     host float [3], finite and > 0
+ * Allocates and synchronizes (not inside capture); TACSL_ERR_STATE while a
+ * graph of the plan exists. */
+#define TACSL_MAX_OBS_BINS 256
+int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* tmpl_bin, const float* scale,
+                               float clip);
+
+/* Forward force field with the observation epilogue fused into the per-taxel
+ * pass: writes obs (device float [n_inst][n_bins][3]) and the wrench, and the
+ * per-taxel fields when out->depth, normal, fn and ft are all given; when all
+ * four are NULL they are not written at all (observation only: no per-taxel
+ * HBM traffic).  A mix of NULL and non-NULL fields is TACSL_ERR_NULL_ARG;
+ * TACSL_ERR_STATE when no observation is set.  Same asynchrony rules as
+ * tacsl_force_field; the observation is deterministic (fixed summation order). */
+int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, float* obs,
+                              hipStream_t stream);
+
 /* Reverse mode (hand-written adjoint with recomputation of the forward),
  * enqueued on `stream`; same asynchrony rules as tacsl_force_field. */
 int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* grads,
@@ -253,6 +279,37 @@ int tacsl_plan_timer_read(tacsl_plan plan, int32_t max, int32_t* n, float* ms);
 
 /* Release the plan's device memory (synchronizes its device).  NULL is a no-op. */
 int tacsl_plan_destroy(tacsl_plan plan);
+
+/* Implicit soft-contact impulse, batched over contacts (Section III-A,
+ * "Constraint Solution": the Kelvin-Voigt law imposed at the end of the step,
+ * solved in closed form with the semi-implicit Euler update).  For contact k
+ * with contact distance eps (negative when interpenetrating), separation
+ * velocity eps_dot, inverse effective inertia inv_mass = 1/m (0 for an
+ * immovable body) and the stiffness and damping (kappa, c) of its
+ * environment:
+ *   alpha     = dt (dt kappa + c)
+ *   lambda[k] = max(0, (-dt kappa eps - alpha eps_dot) / (1 + alpha inv_mass))
+ *   dv[k]     = lambda[k] inv_mass       (the change of eps_dot over the step)
+ * Arguments (FP32 unless noted; all arrays device memory, caller-owned):
+ *   n         contacts (>= 0)
+ *   eps, eps_dot, inv_mass  [n]
+ *   env       int32 [n] environment of each contact, or NULL (all use row 0)
+ *   n_env     rows of kc (>= 1)
+ *   kc        [n_env][2] = (kappa, c), 8-byte aligned
+ *   dt        step length, finite and > 0
+ *   lambda    [n] out: impulse (N s); dv [n] out or NULL
+ *   status    optional device word: TACSL_DEV_BAD_CONTACT is OR-ed in when a
+ *             contact is invalid (env outside [0, n_env), a non-finite input or
+ *             result, or 1 + alpha inv_mass <= 0); such a contact gets
+ *             lambda = dv = 0
+ * Errors: TACSL_ERR_SHAPE (n < 0 or n_env < 1), TACSL_ERR_RANGE (dt, kc
+ * alignment), TACSL_ERR_NULL_ARG (a required array NULL while n > 0),
+ * TACSL_ERR_HIP (launch failed).  Asynchronous on `stream`; no allocation,
+ * no host synchronization, capturable in a HIP graph.  16-byte aligned
+ * arrays take the four-contacts-per-lane path. */
+int tacsl_contact_impulse(int64_t n, const float* eps, const float* eps_dot, const float* inv_mass,
+                          const int32_t* env, int32_t n_env, const float* kc, float dt, float* lambda, float* dv,
+                          uint32_t* status, hipStream_t stream);
 
 #ifdef __cplusplus
 }

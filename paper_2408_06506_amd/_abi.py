@@ -22,13 +22,16 @@ STATUS_NAMES = {
 }
 DEV_NONFINITE_POSE = 0x1
 DEV_ZERO_QUAT = 0x2
+DEV_BAD_CONTACT = 0x4
 
 EXPORTS = [
     "tacsl_abi_version", "tacsl_status_string", "tacsl_validate_scene", "tacsl_build_worklist",
     "tacsl_plan_create", "tacsl_plan_set_tuning", "tacsl_plan_get_info", "tacsl_plan_offsets",
     "tacsl_force_field", "tacsl_force_field_backward", "tacsl_graph_create", "tacsl_graph_launch",
     "tacsl_graph_destroy", "tacsl_plan_timer_start", "tacsl_plan_timer_read", "tacsl_plan_destroy",
+    "tacsl_contact_impulse", "tacsl_plan_set_observation", "tacsl_force_field_observe",
 ]
+MAX_OBS_BINS = 256
 
 
 class SceneDesc(ctypes.Structure):
@@ -102,6 +105,9 @@ def load():
     lib.tacsl_plan_timer_start.argtypes = [P, I32]
     lib.tacsl_plan_timer_read.argtypes = [P, I32, P, P]
     lib.tacsl_plan_destroy.argtypes = [P]
+    lib.tacsl_plan_set_observation.argtypes = [P, I32, P, P, ctypes.c_float]
+    lib.tacsl_force_field_observe.argtypes = [P, P, P, P, P]
+    lib.tacsl_contact_impulse.argtypes = [I64, P, P, P, P, I32, P, ctypes.c_float, P, P, P, P]
     for name in EXPORTS:
         if name not in ("tacsl_status_string",):
             getattr(lib, name).restype = ctypes.c_int

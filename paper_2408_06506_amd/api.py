@@ -129,6 +129,8 @@ class Plan:
         self.n_inst = self._hs.n_inst
         info = self.info()
         self.n_taxels = int(info.n_taxels)
+        self._tmpl_T = int(self._hs.tmpl_offset[-1]) if self._hs.tmpl_offset.size else 0
+        self.obs_bins = 0
         self._graphs: List["SubstepGraph"] = []
 
     # -- inspection --------------------------------------------------------
@@ -217,6 +219,52 @@ class Plan:
         _abi.check(self._lib.tacsl_force_field(self._plan, ctypes.byref(s), ctypes.byref(o),
                                                _stream_handle(stream)), "tacsl_force_field")
         return out
+
+    def set_observation(self, tmpl_bin, n_bins: int, scale=(1.0, 1.0, 1.0), clip: float = 0.0):
+        """Install the observation epilogue: per pad and bin the mean of
+        (|f_n|, f_t,x, f_t,y) over the bin's taxels, / scale, clipped to +-clip.
+        ``tmpl_bin``: int32 bin of each template taxel (-1: none); n_bins = 0 removes it."""
+        tb = np.zeros(0, np.int32) if tmpl_bin is None else _np(tmpl_bin, np.int32).reshape(-1)
+        if n_bins and tb.size != self._tmpl_T:
+            raise ValueError(f"tmpl_bin must hold {self._tmpl_T} entries")
+        sc = _np(scale, np.float32).reshape(3)
+        _abi.check(self._lib.tacsl_plan_set_observation(self._plan, int(n_bins), tb.ctypes.data if tb.size else None,
+                                                        sc.ctypes.data,
+                                                        float(clip)), "tacsl_plan_set_observation")
+        self.obs_bins = int(n_bins)
+
+    def new_observation(self) -> torch.Tensor:
+        return torch.empty(self.n_inst, self.obs_bins, 3, device=self.device, dtype=torch.float32)
+
+    def observe(self, st: Dict[str, torch.Tensor], obs: Optional[torch.Tensor] = None,
+                out: Optional[Dict[str, torch.Tensor]] = None, fields: bool = False, stream=None):
+        """Forward pass with the fused observation epilogue.  With fields=False
+        (and no ``out`` fields) only the observation and the wrench are written.
+        Returns (obs, out)."""
+        self._check_state(st)
+        if not self.obs_bins:
+            raise RuntimeError("no observation set on this plan (call set_observation first)")
+        if obs is None:
+            obs = self.new_observation()
+        if (obs.dtype != torch.float32 or not obs.is_contiguous() or tuple(obs.shape) != (self.n_inst, self.obs_bins, 3)
+                or obs.device != self.device):
+            raise ValueError(f"obs must be a contiguous float32 ({self.n_inst}, {self.obs_bins}, 3) tensor")
+        if out is None:
+            if fields:
+                out = self.new_outputs()
+            else:
+                f = dict(device=self.device, dtype=torch.float32)
+                out = dict(wrench=torch.empty(self.n_inst, 6, **f),
+                           status=torch.zeros(1, device=self.device, dtype=torch.int32))
+        if "depth" in out:
+            self._check_outputs(out)
+            o = self._out_struct(out)
+        else:
+            o = _abi.Outputs(None, None, None, None, _ptr(out["wrench"]), _ptr(out.get("status")))
+        s = self._state_struct(st)
+        _abi.check(self._lib.tacsl_force_field_observe(self._plan, ctypes.byref(s), ctypes.byref(o), _ptr(obs),
+                                                       _stream_handle(stream)), "tacsl_force_field_observe")
+        return obs, out
 
     def backward(self, st: Dict[str, torch.Tensor], w_fn: torch.Tensor, w_ft: torch.Tensor,
                  grads: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
@@ -340,3 +388,38 @@ def force_field(plan: Plan, pad_pose, obj_pose, pad_twist, obj_twist, params, ob
     depth, normal and wrench are not differentiable.
     """
     return _ForceFieldFn.apply(plan, pad_pose, obj_pose, pad_twist, obj_twist, params, obj_pose_delta)
+
+
+def contact_impulse(eps: torch.Tensor, eps_dot: torch.Tensor, inv_mass: torch.Tensor, kc: torch.Tensor, dt: float,
+                    env: Optional[torch.Tensor] = None, lam: Optional[torch.Tensor] = None,
+                    dv: Optional[torch.Tensor] = None, with_dv: bool = True, status: Optional[torch.Tensor] = None,
+                    stream=None):
+    """Batched implicit soft-contact impulse (Section III-A, closed form of the
+    end-of-step Kelvin-Voigt law), enqueued on the current torch stream.
+
+    eps, eps_dot, inv_mass: float32 [n]; kc: float32 [n_env, 2] = (kappa, c);
+    env: int32 [n] or None.  Returns (lambda, dv) (dv None when with_dv is False).
+    """
+    lib = _abi.load()
+    n = int(eps.numel())
+    dev = eps.device
+    for name, t in (("eps", eps), ("eps_dot", eps_dot), ("inv_mass", inv_mass)):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n or t.device != dev:
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements on {dev}")
+    if kc.dtype != torch.float32 or not kc.is_contiguous() or kc.dim() != 2 or kc.shape[1] != 2 or kc.device != dev:
+        raise ValueError("kc must be a contiguous float32 (n_env, 2) tensor on the contacts' device")
+    if env is not None and (env.dtype != torch.int32 or not env.is_contiguous() or env.numel() != n
+                            or env.device != dev):
+        raise ValueError(f"env must be a contiguous int32 tensor of {n} elements on {dev}")
+    if lam is None:
+        lam = torch.empty(n, device=dev, dtype=torch.float32)
+    if dv is None and with_dv:
+        dv = torch.empty(n, device=dev, dtype=torch.float32)
+    for name, t in (("lam", lam), ("dv", dv)):
+        if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n
+                              or t.device != dev):
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {n} elements on {dev}")
+    _abi.check(lib.tacsl_contact_impulse(n, _ptr(eps), _ptr(eps_dot), _ptr(inv_mass), _ptr(env), int(kc.shape[0]),
+                                         _ptr(kc), float(dt), _ptr(lam), _ptr(dv), _ptr(status),
+                                         _stream_handle(stream)), "tacsl_contact_impulse")
+    return lam, dv

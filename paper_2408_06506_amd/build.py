@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtacsl.so")
-SOURCES = [os.path.join(CSRC, "tacsl_plan.cpp"), os.path.join(CSRC, "tacsl_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "tacsl_plan.cpp"), os.path.join(CSRC, "tacsl_kernels.hip"),
+           os.path.join(CSRC, "tacsl_impulse.hip")]
 ARCH = "gfx950"
 
 

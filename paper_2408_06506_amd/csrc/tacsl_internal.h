@@ -81,6 +81,24 @@ struct FwdArgs {
   float* ft;             // [3][T]
   int64_t T;
   float* partial;        // [n_tiles][6] wrench partials (the wrench itself when tiles == pads)
+  int32_t mode;          // 1: per-taxel fields; 2: observation pooling; 3: both
+  const int32_t* obs_bin;  // [tmpl_T] bin of each template taxel (-1: none), observation modes
+  int32_t obs_n;           // bins per pad
+  float* obs_partial;      // [n_tiles][obs_n][3] pooled channel sums
+};
+
+// Observation epilogue: per pad and bin, channels (|f_n|, f_t,x, f_t,y)
+// averaged over the bin's taxels, divided by scale, clipped to +-clip.
+struct ObsReduceArgs {
+  const int64_t* inst_tile_begin;  // [n_inst+1]
+  const float* partial;            // [n_tiles][obs_n][3]
+  const int32_t* inst_tmpl;        // [n_inst]
+  const float* icnt;               // [n_tmpl][obs_n] 1 / taxels in the bin (0 for an empty bin)
+  float scale[3];                  // per channel, > 0
+  float clip;                      // <= 0: no clipping
+  int32_t obs_n;
+  int32_t n_inst;
+  float* obs;                      // [n_inst][obs_n][3]
 };
 
 struct WrenchReduceArgs {
@@ -129,6 +147,7 @@ hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, in
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream);
 hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream);
 hipError_t launch_wrench_reduce(const WrenchReduceArgs& a, hipStream_t stream);
+hipError_t launch_obs_reduce(const ObsReduceArgs& a, hipStream_t stream);
 hipError_t launch_backward(const BwdArgs& a, int block, int grid, hipStream_t stream);
 hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t stream);
 

@@ -260,11 +260,14 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   f.tx = f.ux - (float)cx;
   f.ty = f.uy - (float)cy;
   f.tz = f.uz - (float)cz;
-  // per-lane offsets of the two x-nodes; y steps are scalar, z steps immediate
-  const uint32_t yz = (uint32_t)cy * st.stride_y + (uint32_t)cz * 32u;
+  // per-lane offsets of the two x-nodes; y steps are scalar, z steps
+  // immediate.  Plan creation keeps stride_q = 32 ny nz below 2^24 (and so
+  // stride_y and the cell indices), so the products fit the full-rate 24-bit
+  // multiplier.
+  const uint32_t yz = __umul24((uint32_t)cy, st.stride_y) + (uint32_t)cz * 32u;
   const uint32_t x0 = (uint32_t)cx, x1 = x0 + 1u;
-  const uint32_t o0 = (x0 >> 1) * st.stride_q + (x0 & 1u) * 16u + yz;
-  const uint32_t o1 = (x1 >> 1) * st.stride_q + (x1 & 1u) * 16u + yz;
+  const uint32_t o0 = __umul24(x0 >> 1, st.stride_q) + (x0 & 1u) * 16u + yz;
+  const uint32_t o1 = __umul24(x1 >> 1, st.stride_q) + (x1 & 1u) * 16u + yz;
   const uint32_t sy = st.stride_y;
   f.c[0] = load_node(rs, o0, 0u);
   f.c[1] = load_node(rs, o1, 0u);
@@ -329,15 +332,88 @@ __device__ __forceinline__ int next_slot(int slot, int dynamic, int32_t* queue, 
 // Tile records are read at a workgroup-uniform index through restrict
 // (read-only, non-aliased) pointers, so they land in scalar registers and the
 // buffer resource of the grid is uniform (no per-lane waterfall).
-template <int BLOCK>
+// Output pointers of one tile (SoA, taxel k of the tile at element k).
+struct TileOut {
+  float *d, *n0, *n1, *n2, *f0, *f1, *f2, *t0, *t1, *t2;
+};
+
+// One taxel of the forward path: evaluation, optional SoA stores, wrench
+// accumulation.  Returns the observation channels (|f_n|, f_t,x, f_t,y).
+template <bool FIELDS>
+__device__ __forceinline__ void taxel_step(const InstXf& x, const InstStatic& st, __amdgpu_buffer_rsrc_t rs,
+                                           const float* tx, const float* ty, const float* tz, uint32_t k,
+                                           const TileOut& o, float acc[6], float ch[3]) {
+  // uniform 64-bit base + 32-bit lane offset: saddr addressing, no 64-bit VALU math
+  const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
+  TaxelFwd f;
+  taxel_forward(x, st, rs, px, py, pz, f);
+  float dep = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+  float fn0 = 0.f, fn1 = 0.f, fn2 = 0.f, ft0 = 0.f, ft1 = 0.f, ft2 = 0.f, sn = 0.f;
+  if (f.contact) dep = -f.phi;
+  if (f.force) {
+    n0 = f.n[0]; n1 = f.n[1]; n2 = f.n[2];
+    fn0 = f.fn[0]; fn1 = f.fn[1]; fn2 = f.fn[2];
+    ft0 = f.ft[0]; ft1 = f.ft[1]; ft2 = f.ft[2];
+    sn = fabsf(f.s);
+  }
+  if constexpr (FIELDS) {
+    put(o.d, k, dep);
+    put(o.n0, k, n0); put(o.n1, k, n1); put(o.n2, k, n2);
+    put(o.f0, k, fn0); put(o.f1, k, fn1); put(o.f2, k, fn2);
+    put(o.t0, k, ft0); put(o.t1, k, ft1); put(o.t2, k, ft2);
+  }
+  const float F0 = fn0 + ft0, F1 = fn1 + ft1, F2 = fn2 + ft2;
+  acc[0] += F0;
+  acc[1] += F1;
+  acc[2] += F2;
+  acc[3] += fmaf(py, F2, -pz * F1);
+  acc[4] += fmaf(pz, F0, -px * F2);
+  acc[5] += fmaf(px, F1, -py * F0);
+  ch[0] = sn;
+  ch[1] = ft0;
+  ch[2] = ft1;
+}
+
+// Deterministic per-wave pooling: for each distinct bin among the lanes (in
+// order of the lowest lane holding it) the lanes of that bin are summed with
+// a fixed butterfly and lane 0 adds the sums to the wave's accumulator row.
+// Needs every lane of the wave active; b < 0 means no bin.
+__device__ __forceinline__ void pool_wave(float* acc, int lane, int b, const float ch[3]) {
+  uint64_t pending = __ballot(b >= 0);
+  while (pending) {
+    const int lead = __ffsll((unsigned long long)pending) - 1;
+    const int bb = __builtin_amdgcn_readlane(b, lead);
+    const bool mine = b == bb;
+    const float s0 = wave_sum(mine ? ch[0] : 0.f);
+    const float s1 = wave_sum(mine ? ch[1] : 0.f);
+    const float s2 = wave_sum(mine ? ch[2] : 0.f);
+    if (lane == 0) {
+      acc[3 * bb] += s0;
+      acc[3 * bb + 1] += s1;
+      acc[3 * bb + 2] += s2;
+    }
+    pending &= ~__ballot(mine);
+  }
+}
+
+// MODE bits: kFields writes the per-taxel SoA fields; kObserve pools the
+// observation channels per bin into per-tile partials (dynamic LDS of
+// BLOCK/64 * obs_n * 3 floats).
+constexpr int kFields = 1;
+constexpr int kObserve = 2;
+
+template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_force_fwd(
     const Tile* __restrict__ tiles, const int32_t* __restrict__ order, int32_t n_tiles, int32_t dynamic,
     int32_t* __restrict__ queue, const InstStatic* __restrict__ stat, const InstXf* __restrict__ xfs,
     const float* __restrict__ tmpl, int64_t tmpl_T, float* __restrict__ depth, float* __restrict__ normal,
-    float* __restrict__ fn, float* __restrict__ ft, int64_t T, float* __restrict__ partial) {
+    float* __restrict__ fn, float* __restrict__ ft, int64_t T, float* __restrict__ partial,
+    const int32_t* __restrict__ obs_bin, int32_t obs_n, float* __restrict__ obs_partial) {
   constexpr int NW = BLOCK / 64;
+  constexpr bool FIELDS = (MODE & kFields) != 0;
   __shared__ float red[NW][6];
   __shared__ int s_next;
+  extern __shared__ float obs_acc[];  // [NW][obs_n * 3], kObserve only
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int slot = blockIdx.x;
@@ -350,42 +426,41 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(
     const float* tx = tmpl + st.tmpl_off + tl.k0;
     const float* ty = tx + tmpl_T;
     const float* tz = ty + tmpl_T;
-    const int64_t ob = st.out_off + tl.k0;
-    float* o_d = depth + ob;
-    float* o_n0 = normal + ob;
-    float* o_n1 = o_n0 + T;
-    float* o_n2 = o_n1 + T;
-    float* o_f0 = fn + ob;
-    float* o_f1 = o_f0 + T;
-    float* o_f2 = o_f1 + T;
-    float* o_t0 = ft + ob;
-    float* o_t1 = o_t0 + T;
-    float* o_t2 = o_t1 + T;
+    TileOut o{};
+    if constexpr (FIELDS) {
+      const int64_t ob = st.out_off + tl.k0;
+      o.d = depth + ob;
+      o.n0 = normal + ob;
+      o.n1 = o.n0 + T;
+      o.n2 = o.n1 + T;
+      o.f0 = fn + ob;
+      o.f1 = o.f0 + T;
+      o.f2 = o.f1 + T;
+      o.t0 = ft + ob;
+      o.t1 = o.t0 + T;
+      o.t2 = o.t1 + T;
+    }
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK) {
-      // uniform 64-bit base + 32-bit lane offset: saddr addressing, no 64-bit VALU math
-      const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
-      TaxelFwd f;
-      taxel_forward(x, st, rs, px, py, pz, f);
-      float dep = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
-      float fn0 = 0.f, fn1 = 0.f, fn2 = 0.f, ft0 = 0.f, ft1 = 0.f, ft2 = 0.f;
-      if (f.contact) dep = -f.phi;
-      if (f.force) {
-        n0 = f.n[0]; n1 = f.n[1]; n2 = f.n[2];
-        fn0 = f.fn[0]; fn1 = f.fn[1]; fn2 = f.fn[2];
-        ft0 = f.ft[0]; ft1 = f.ft[1]; ft2 = f.ft[2];
+    float ch[3];
+    if constexpr ((MODE & kObserve) != 0) {
+      const int row = obs_n * 3;
+      for (int j = threadIdx.x; j < NW * row; j += BLOCK) obs_acc[j] = 0.f;
+      __syncthreads();
+      const int32_t* bins = obs_bin + st.tmpl_off + tl.k0;
+      // whole-block strides so that every lane takes part in the pooling
+      for (uint32_t base = 0; base < (uint32_t)tl.count; base += BLOCK) {
+        const uint32_t k = base + threadIdx.x;
+        int b = -1;
+        ch[0] = ch[1] = ch[2] = 0.f;
+        if (k < (uint32_t)tl.count) {
+          taxel_step<FIELDS>(x, st, rs, tx, ty, tz, k, o, acc, ch);
+          b = bins[k];
+        }
+        pool_wave(obs_acc + wave * row, lane, b, ch);
       }
-      put(o_d, k, dep);
-      put(o_n0, k, n0); put(o_n1, k, n1); put(o_n2, k, n2);
-      put(o_f0, k, fn0); put(o_f1, k, fn1); put(o_f2, k, fn2);
-      put(o_t0, k, ft0); put(o_t1, k, ft1); put(o_t2, k, ft2);
-      const float F0 = fn0 + ft0, F1 = fn1 + ft1, F2 = fn2 + ft2;
-      acc[0] += F0;
-      acc[1] += F1;
-      acc[2] += F2;
-      acc[3] += fmaf(py, F2, -pz * F1);
-      acc[4] += fmaf(pz, F0, -px * F2);
-      acc[5] += fmaf(px, F1, -py * F0);
+    } else {
+      for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK)
+        taxel_step<FIELDS>(x, st, rs, tx, ty, tz, k, o, acc, ch);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -399,8 +474,33 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(
       for (int w = 0; w < NW; ++w) s += red[w][threadIdx.x];
       partial[6 * (int64_t)tid + threadIdx.x] = s;
     }
+    if constexpr ((MODE & kObserve) != 0) {
+      const int row = obs_n * 3;
+      float* dst = obs_partial + (int64_t)tid * row;
+      for (int j = threadIdx.x; j < row; j += BLOCK) {
+        float s = 0.f;
+        for (int w = 0; w < NW; ++w) s += obs_acc[w * row + j];
+        dst[j] = s;
+      }
+    }
     slot = next_slot<BLOCK>(slot, dynamic, queue, &s_next);
   }
+}
+
+// Observation of each pad: the pad's tile partials summed in tile order,
+// divided by the bin's taxel count and the channel scale, clipped.
+__global__ __launch_bounds__(256) void k_obs_reduce(const ObsReduceArgs a) {
+  const int row = a.obs_n * 3;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_inst * row) return;
+  const int i = (int)(idx / row);
+  const int j = (int)(idx - (int64_t)i * row);
+  float s = 0.f;
+  for (int64_t t = a.inst_tile_begin[i]; t < a.inst_tile_begin[i + 1]; ++t) s += a.partial[t * row + j];
+  const int c = j % 3;
+  float v = s * a.icnt[(int64_t)a.inst_tmpl[i] * a.obs_n + j / 3] / a.scale[c];
+  if (a.clip > 0.f) v = fminf(fmaxf(v, -a.clip), a.clip);
+  a.obs[idx] = v;
 }
 
 __global__ __launch_bounds__(256) void k_wrench_reduce(WrenchReduceArgs a) {
@@ -649,16 +749,34 @@ hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream) {
 
 #define TACSL_FWD_ARGS                                                                                  \
   a.tiles, a.order, a.n_tiles, a.dynamic, a.queue, a.stat, a.xf, a.tmpl, a.tmpl_T, a.depth, a.normal, a.fn, \
-      a.ft, a.T, a.partial
+      a.ft, a.T, a.partial, a.obs_bin, a.obs_n, a.obs_partial
 
-hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream) {
+template <int MODE>
+hipError_t launch_forward_mode(const FwdArgs& a, int block, int grid, hipStream_t stream) {
+  const size_t lds = (MODE & kObserve) ? (size_t)(block / 64) * a.obs_n * 3 * sizeof(float) : 0;
   switch (block) {
-    case 64: hipLaunchKernelGGL(k_force_fwd<64>, dim3(grid), dim3(64), 0, stream, TACSL_FWD_ARGS); break;
-    case 128: hipLaunchKernelGGL(k_force_fwd<128>, dim3(grid), dim3(128), 0, stream, TACSL_FWD_ARGS); break;
-    case 256: hipLaunchKernelGGL(k_force_fwd<256>, dim3(grid), dim3(256), 0, stream, TACSL_FWD_ARGS); break;
-    case 512: hipLaunchKernelGGL(k_force_fwd<512>, dim3(grid), dim3(512), 0, stream, TACSL_FWD_ARGS); break;
+    case 64: hipLaunchKernelGGL((k_force_fwd<64, MODE>), dim3(grid), dim3(64), lds, stream, TACSL_FWD_ARGS); break;
+    case 128: hipLaunchKernelGGL((k_force_fwd<128, MODE>), dim3(grid), dim3(128), lds, stream, TACSL_FWD_ARGS); break;
+    case 256: hipLaunchKernelGGL((k_force_fwd<256, MODE>), dim3(grid), dim3(256), lds, stream, TACSL_FWD_ARGS); break;
+    case 512: hipLaunchKernelGGL((k_force_fwd<512, MODE>), dim3(grid), dim3(512), lds, stream, TACSL_FWD_ARGS); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream) {
+  switch (a.mode) {
+    case kFields: return launch_forward_mode<kFields>(a, block, grid, stream);
+    case kObserve: return launch_forward_mode<kObserve>(a, block, grid, stream);
+    case kFields | kObserve: return launch_forward_mode<kFields | kObserve>(a, block, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_obs_reduce(const ObsReduceArgs& a, hipStream_t stream) {
+  const int64_t n = (int64_t)a.n_inst * a.obs_n * 3;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_obs_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

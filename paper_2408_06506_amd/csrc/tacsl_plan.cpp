@@ -18,6 +18,7 @@ using tacsl::Tile;
 namespace {
 
 constexpr int64_t kMaxGridBytes = (int64_t(1) << 32) - 1;  // prepared grid addressed with 32-bit offsets
+constexpr int64_t kMaxPairStride = (int64_t(1) << 24) - 1;  // bytes per x-pair: a 24-bit multiplier operand
 constexpr int64_t kMaxTemplate = int64_t(1) << 30;
 constexpr int kXcdCount = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin across them
 
@@ -54,6 +55,7 @@ int validate(const tacsl_scene_desc* d) {
     const int32_t* n = d->sdf_dims + 3 * g;
     if (n[0] < 2 || n[1] < 2 || n[2] < 2) return TACSL_ERR_SHAPE;
     if (tacsl::prepared_grid_bytes(n[0], n[1], n[2]) > kMaxGridBytes) return TACSL_ERR_UNSUPPORTED;
+    if (int64_t(32) * n[1] * n[2] > kMaxPairStride) return TACSL_ERR_UNSUPPORTED;
     const float h = d->sdf_spacing[g];
     if (!(h > 0.f) || !std::isfinite(h)) return TACSL_ERR_RANGE;
     for (int a = 0; a < 3; ++a)
@@ -186,6 +188,14 @@ struct tacsl_plan_s {
   int32_t* d_queue = nullptr;
   int32_t* d_env_inst_begin = nullptr;
   int32_t* d_env_inst = nullptr;
+  // observation epilogue (set by tacsl_plan_set_observation)
+  int32_t obs_n = 0;
+  float obs_scale[3] = {1.f, 1.f, 1.f};
+  float obs_clip = 0.f;
+  int32_t* d_obs_bin = nullptr;      // [tmpl_T]
+  float* d_obs_icnt = nullptr;       // [n_tmpl][obs_n]
+  int32_t* d_obs_inst_tmpl = nullptr;  // [n_inst]
+  float* d_obs_partial = nullptr;    // [n_tiles][obs_n][3]
   int64_t n_tiles = 0;
   int64_t ws_bytes = 0;
   int live_graphs = 0;
@@ -222,6 +232,14 @@ struct tacsl_plan_s {
     dfree(d_inst_tile_begin);
     dfree(d_partial);
     dfree(d_bpartial);
+    dfree(d_obs_partial);
+  }
+  void free_observation() {
+    dfree(d_obs_bin);
+    dfree(d_obs_icnt);
+    dfree(d_obs_inst_tmpl);
+    dfree(d_obs_partial);
+    obs_n = 0;
   }
   void free_all() {
     free_timer();
@@ -233,6 +251,7 @@ struct tacsl_plan_s {
     dfree(d_queue);
     dfree(d_env_inst_begin);
     dfree(d_env_inst);
+    free_observation();
   }
 };
 
@@ -255,7 +274,8 @@ int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
   const size_t n = tiles.size();
   if (dalloc(&p->d_tiles, n) != hipSuccess || dalloc(&p->d_order, n) != hipSuccess ||
       dalloc(&p->d_inst_tile_begin, itb.size()) != hipSuccess || dalloc(&p->d_partial, 6 * n) != hipSuccess ||
-      dalloc(&p->d_bpartial, (size_t)tacsl::kBwdAcc * n) != hipSuccess) {
+      dalloc(&p->d_bpartial, (size_t)tacsl::kBwdAcc * n) != hipSuccess ||
+      (p->obs_n > 0 && dalloc(&p->d_obs_partial, (size_t)3 * p->obs_n * n) != hipSuccess)) {
     p->free_worklist();
     return TACSL_ERR_ALLOC;
   }
@@ -271,7 +291,7 @@ int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
 }
 
 int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, hipStream_t stream,
-                    bool capturing) {
+                    bool capturing, float* obs = nullptr) {
   if (p->n_inst == 0) return TACSL_OK;
   tacsl::PrologueArgs pa{};
   pa.pad_pose = s->pad_pose;
@@ -287,6 +307,7 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   pa.queue = p->d_queue;
   if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
   const bool direct = p->n_tiles == p->n_inst;  // one tile per pad: tile id == pad id
+  const bool fields = o->depth != nullptr;
   tacsl::FwdArgs fa{};
   fa.tiles = p->d_tiles;
   fa.order = p->d_order;
@@ -303,8 +324,17 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   fa.ft = o->ft;
   fa.T = p->T;
   fa.partial = direct ? o->wrench : p->d_partial;
+  fa.mode = obs ? (fields ? 3 : 2) : 1;  // without the observation the fields are always written
+  fa.obs_bin = p->d_obs_bin;
+  fa.obs_n = obs ? p->obs_n : 0;
+  fa.obs_partial = p->d_obs_partial;
   const int grid = p->tun.schedule == 0 ? (int)p->n_tiles : (int)std::min<int64_t>(p->tun.grid, p->n_tiles);
-  const bool timed = !capturing && p->timing();
+  bool timed = !capturing && p->timing();
+  if (timed) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return TACSL_ERR_HIP;
+    timed = cap == hipStreamCaptureStatusNone;
+  }
   if (timed && hipEventRecord(p->ev_start[p->timer_n], stream) != hipSuccess) return TACSL_ERR_HIP;
   if (tacsl::launch_forward(fa, p->tun.block, grid, stream) != hipSuccess) return TACSL_ERR_HIP;
   if (timed) {
@@ -314,6 +344,19 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   if (!direct) {
     tacsl::WrenchReduceArgs ra{p->d_inst_tile_begin, p->d_partial, o->wrench, p->n_inst};
     if (tacsl::launch_wrench_reduce(ra, stream) != hipSuccess) return TACSL_ERR_HIP;
+  }
+  if (obs) {
+    tacsl::ObsReduceArgs oa{};
+    oa.inst_tile_begin = p->d_inst_tile_begin;
+    oa.partial = p->d_obs_partial;
+    oa.inst_tmpl = p->d_obs_inst_tmpl;
+    oa.icnt = p->d_obs_icnt;
+    for (int c = 0; c < 3; ++c) oa.scale[c] = p->obs_scale[c];
+    oa.clip = p->obs_clip;
+    oa.obs_n = p->obs_n;
+    oa.n_inst = p->n_inst;
+    oa.obs = obs;
+    if (tacsl::launch_obs_reduce(oa, stream) != hipSuccess) return TACSL_ERR_HIP;
   }
   return TACSL_OK;
 }
@@ -541,6 +584,70 @@ int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_out
   rc = check_outputs(plan, out);
   if (rc != TACSL_OK) return rc;
   return enqueue_forward(plan, state, out, stream, false);
+}
+
+int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* tmpl_bin, const float* scale,
+                               float clip) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (plan->live_graphs > 0) return TACSL_ERR_STATE;
+  if (n_bins == 0) {
+    if (hipDeviceSynchronize() != hipSuccess) return TACSL_ERR_HIP;
+    plan->free_observation();
+    return TACSL_OK;
+  }
+  if (n_bins < 0 || n_bins > TACSL_MAX_OBS_BINS) return TACSL_ERR_RANGE;
+  if (!scale || (plan->tmpl_T > 0 && !tmpl_bin)) return TACSL_ERR_NULL_ARG;
+  for (int c = 0; c < 3; ++c)
+    if (!(scale[c] > 0.f) || !std::isfinite(scale[c])) return TACSL_ERR_RANGE;
+  if (!std::isfinite(clip)) return TACSL_ERR_RANGE;
+  const int64_t TT = plan->tmpl_T;
+  std::vector<float> icnt((size_t)plan->n_tmpl * n_bins, 0.f);
+  for (int p = 0; p < plan->n_tmpl; ++p) {
+    for (int64_t k = plan->tmpl_offset[p]; k < plan->tmpl_offset[p + 1]; ++k) {
+      const int32_t b = tmpl_bin[k];
+      if (b < -1 || b >= n_bins) return TACSL_ERR_RANGE;
+      if (b >= 0) icnt[(size_t)p * n_bins + b] += 1.f;
+    }
+  }
+  for (float& v : icnt) v = v > 0.f ? 1.f / v : 0.f;
+  if (hipDeviceSynchronize() != hipSuccess) return TACSL_ERR_HIP;
+  plan->free_observation();
+  if (dalloc(&plan->d_obs_bin, (size_t)TT) != hipSuccess || dalloc(&plan->d_obs_icnt, icnt.size()) != hipSuccess ||
+      dalloc(&plan->d_obs_inst_tmpl, (size_t)plan->n_inst) != hipSuccess ||
+      dalloc(&plan->d_obs_partial, (size_t)3 * n_bins * plan->n_tiles) != hipSuccess) {
+    plan->free_observation();
+    return TACSL_ERR_ALLOC;
+  }
+  if ((TT > 0 && hipMemcpy(plan->d_obs_bin, tmpl_bin, (size_t)TT * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                     hipSuccess) ||
+      (!icnt.empty() && hipMemcpy(plan->d_obs_icnt, icnt.data(), icnt.size() * sizeof(float),
+                                  hipMemcpyHostToDevice) != hipSuccess) ||
+      (plan->n_inst > 0 && hipMemcpy(plan->d_obs_inst_tmpl, plan->inst_tmpl.data(),
+                                     (size_t)plan->n_inst * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)) {
+    plan->free_observation();
+    return TACSL_ERR_HIP;
+  }
+  plan->obs_n = n_bins;
+  for (int c = 0; c < 3; ++c) plan->obs_scale[c] = scale[c];
+  plan->obs_clip = clip;
+  return TACSL_OK;
+}
+
+int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, float* obs,
+                              hipStream_t stream) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (plan->obs_n == 0) return TACSL_ERR_STATE;
+  int rc = check_state(plan, state);
+  if (rc != TACSL_OK) return rc;
+  if (!out) return TACSL_ERR_NULL_ARG;
+  const int given = (out->depth != nullptr) + (out->normal != nullptr) + (out->fn != nullptr) + (out->ft != nullptr);
+  if (given != 0 && given != 4) return TACSL_ERR_NULL_ARG;
+  if (plan->n_inst > 0 && (!out->wrench || !obs)) return TACSL_ERR_NULL_ARG;
+  if (given == 4) {
+    rc = check_outputs(plan, out);
+    if (rc != TACSL_OK) return rc;
+  }
+  return enqueue_forward(plan, state, out, stream, false, obs);
 }
 
 int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* g,

@@ -1,0 +1,46 @@
+"""Writes sdf_footprint.json: the number of distinct scalar SDF nodes that the
+taxel stencils of one step touch (trilinear corners of every taxel's cell plus,
+for taxels in contact, the central-difference neighbours of those corners),
+counted by the FP64 oracle on the seeded workloads at step 0.
+
+These counts enter the compulsory-byte figure of the benchmark (4 bytes per
+distinct node of an FP32 field).  Run:  python tests/golden/make_sdf_footprint.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2408_06506_amd import workloads as wl  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sdf_footprint.json")
+
+WORKLOADS = {
+    "roofline_8192x2x80x100_256": wl.make_c3,
+    "differentiation_1024x2x40x50_128": wl.make_c5,
+    "scale_1024x2x40x50_128": wl.make_c2,
+}
+
+
+def main():
+    out = {"source": "Distinct scalar SDF nodes touched by the taxel stencils of step 0 (trilinear corners; "
+                     "central-difference neighbours of the corners for taxels in contact), counted by the FP64 "
+                     "oracle; written by tests/golden/make_sdf_footprint.py",
+           "workloads": {}}
+    for name, make in WORKLOADS.items():
+        t0 = time.time()
+        sc = make()
+        v = oracle.footprint(sc, oracle.state64(sc))
+        out["workloads"][name] = {"n_taxels": int(sc.n_taxels), "n_inst": int(sc.n_inst), "nodes": int(v)}
+        print(f"{name}: {v} nodes for {sc.n_taxels} taxels ({time.time() - t0:.1f}s)", flush=True)
+    with open(OUT, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -26,7 +26,7 @@ def _header_functions():
 def test_library_exports_every_declared_symbol():
     lib = _abi.load()
     names = _header_functions()
-    assert len(names) == 16
+    assert len(names) == 19
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(_abi.EXPORTS) == names
@@ -111,6 +111,13 @@ def test_invalid_descriptions_return_codes():
     dims[0] = (644, 645, 645)
     assert copy_bytes(dims[0]) < 2 ** 32
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == 0
+    # one x-pair slab (32 ny nz bytes) must stay below 2^24 bytes
+    dims[0] = (2, 800, 800)
+    assert copy_bytes(dims[0]) < 2 ** 32 and 32 * 800 * 800 >= 2 ** 24
+    assert api.validate_scene(_mut(sc, sdf_dims=dims)) == -6
+    dims[0] = (4, 724, 723)
+    assert 32 * 724 * 723 < 2 ** 24
+    assert api.validate_scene(_mut(sc, sdf_dims=dims)) == 0
     # counts
     assert api.validate_scene(_mut(sc, n_env=-1)) == -2
 
@@ -177,3 +184,24 @@ def test_bad_tunings_rejected():
         assert ei.value.code == -3
     with pytest.raises(_abi.TacslError):
         api.build_worklist(sc, None, xcd_count=0)
+
+
+def test_contact_impulse_host_validation():
+    """Argument checks of tacsl_contact_impulse return before any launch."""
+    lib = _abi.load()
+    f = lib.tacsl_contact_impulse
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every call below is rejected on the host
+    args = lambda n, n_env=1, dt=1e-3, kc=fake, eps=fake, lam=fake: (n, eps, fake, fake, None, n_env, kc, dt, lam,
+                                                                      None, None, None)
+    assert f(*args(-1)) == -2
+    assert f(*args(10, n_env=0)) == -2
+    assert f(*args(10, dt=0.0)) == -3
+    assert f(*args(10, dt=-1e-3)) == -3
+    assert f(*args(10, dt=float("nan"))) == -3
+    assert f(*args(10, dt=float("inf"))) == -3
+    assert f(*args(0)) == 0                       # nothing to do, nothing launched
+    assert f(*args(0, eps=None, lam=None)) == 0
+    assert f(*args(10, eps=None)) == -1
+    assert f(*args(10, lam=None)) == -1
+    assert f(*args(10, kc=None)) == -1
+    assert f(*args(10, kc=ctypes.c_void_p(4100))) == -3   # (kappa, c) rows must be 8-byte aligned
