@@ -45,6 +45,33 @@ def log(msg):
 FOOTPRINT = os.path.join(ROOT, "tests", "golden", "sdf_footprint.json")
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_force_fwd_roofline_8192x2x80x100_256.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_06506_amd", "csrc", f) for f in ("tacsl_kernels.hip", "tacsl_internal.h")]
+
+
+def measured_traffic(tuning):
+    """HBM bytes per launch of the forward kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the kernel
+    sources or the tuning differ from those the counters were taken with."""
+    import hashlib
+    try:
+        rec = {}
+        for line in open(PROFILE):
+            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha1", "tuning"):
+                k, v = line.split(":", 1)
+                rec[k] = v.strip()
+        h = hashlib.sha1()
+        for f in KERNEL_SOURCES:
+            h.update(open(f, "rb").read())
+        if rec.get("kernel_source_sha1") != h.hexdigest()[:16]:
+            return None
+        if json.loads(rec["tuning"]) != dict(tuning):
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def sdf_footprint_nodes(key, scene):
     """Distinct scalar SDF nodes touched by one step's taxel stencils, as
     counted once for the seeded workload and stored with the test fixtures."""
@@ -105,7 +132,7 @@ def run_main(args, torch, api, wl, autotune):
     achieved = B / (k_avg * 1e-3)
     contact = float((out["depth"] > 0).float().mean().item())
     log(f"{ms_step:.4f} ms/step, kernel {k_avg:.4f} ms, {achieved / 1e9:.1f} GB/s, contact {contact:.3f}")
-    return dict(scene=sc, plan=plan, state=st, out=out, tuning=plan.tuning(), ms_step=ms_step,
+    return dict(scene=sc, plan=plan, state=st, out=out, tuning=plan.tuning, ms_step=ms_step,
                 value=value, kernel_ms=k_avg, kernel_ms_all=kms, bytes=B, footprint=V, achieved=achieved,
                 contact=contact)
 
@@ -376,14 +403,17 @@ def main():
         del src, dst
     m = run_main(args, torch, api, wl, autotune)
     sc = m["scene"]
-    traffic = None
+    traffic = measured_traffic(m["tuning"])
     observation = None
     if not args.no_observation:
         observation = run_observation(args, torch, api, wl, sc, m["tuning"])
     roof = {"bound": "hbm", "achieved": m["achieved"] / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": m["achieved"] / HBM_PEAK, "traffic": traffic, "kernel": "k_force_fwd",
             "kernel_avg_ms": m["kernel_ms"], "algorithmic_bytes_per_launch": m["bytes"],
-            "bytes_per_taxel": m["bytes"] / sc.n_taxels, "sdf_footprint_nodes": m["footprint"]}
+            "bytes_per_taxel": m["bytes"] / sc.n_taxels, "sdf_footprint_nodes": m["footprint"],
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; null if the kernel or "
+                            "tuning changed since the counters were taken)",
+            "traffic_GBps": None if traffic is None else traffic / (m["kernel_ms"] * 1e-3) / 1e9}
     m["plan"].close()
     del m["out"]
     torch.cuda.empty_cache()

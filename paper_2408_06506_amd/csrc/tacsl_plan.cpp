@@ -78,7 +78,7 @@ int resolve_tuning(const tacsl_tuning* in, int cu_count, tacsl_tuning* out) {
   if (t.tile_taxels < 0 || (t.tile_taxels > 0 && t.tile_taxels < 64) || t.tile_taxels > kMaxTemplate)
     return TACSL_ERR_RANGE;
   if (t.schedule < 0 || t.schedule > 2) return TACSL_ERR_RANGE;
-  if (t.order < 0 || t.order > 3) return TACSL_ERR_RANGE;
+  if (t.order < 0 || t.order > 4) return TACSL_ERR_RANGE;
   if (t.grid < 0) return TACSL_ERR_RANGE;
   if (t.grid == 0) t.grid = std::max(1, cu_count) * 8;
   *out = t;
@@ -116,33 +116,52 @@ int make_worklist(const tacsl_scene_desc& d, const tacsl_tuning& t, int xcd, std
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
       return d.env_sdf[d.inst_env[tiles[a].inst]] < d.env_sdf[d.inst_env[tiles[b].inst]];
     });
-  } else if (t.order == 1 && n > 0) {
-    // group by object grid, cut into xcd contiguous segments of equal cost,
-    // interleave so that slot s runs on XCD s % xcd while segments last
+  } else if ((t.order == 1 || t.order == 4) && n > 0) {
+    // group by object grid.  Order 1: cut the whole list into xcd contiguous
+    // segments of equal cost, interleaved so that slot s runs on XCD s % xcd
+    // while segments last.  Order 4: the same per object grid, one object
+    // after the other (object-major for the memory-side cache, and each XCD
+    // on a contiguous run of the object's pads for its own L2).
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
       return d.env_sdf[d.inst_env[tiles[a].inst]] < d.env_sdf[d.inst_env[tiles[b].inst]];
     });
-    int64_t total = 0;
-    for (int32_t tid : order) total += cost(tid);
-    std::vector<std::vector<int32_t>> seg((size_t)xcd);
-    int64_t acc = 0;
-    int x = 0;
-    for (int32_t tid : order) {
-      while (x < xcd - 1 && acc >= (total * (x + 1)) / xcd) ++x;
-      seg[x].push_back(tid);
-      acc += cost(tid);
+    auto interleave = [&](const std::vector<int32_t>& part, std::vector<int32_t>& dst) {
+      int64_t total = 0;
+      for (int32_t tid : part) total += cost(tid);
+      std::vector<std::vector<int32_t>> seg((size_t)xcd);
+      int64_t acc = 0;
+      int x = 0;
+      for (int32_t tid : part) {
+        while (x < xcd - 1 && acc >= (total * (x + 1)) / xcd) ++x;
+        seg[x].push_back(tid);
+        acc += cost(tid);
+      }
+      std::vector<size_t> pos((size_t)xcd, 0);
+      bool more = true;
+      while (more) {
+        more = false;
+        for (int s2 = 0; s2 < xcd; ++s2)
+          if (pos[s2] < seg[s2].size()) {
+            dst.push_back(seg[s2][pos[s2]++]);
+            more = true;
+          }
+      }
+    };
+    std::vector<int32_t> out;
+    out.reserve(order.size());
+    if (t.order == 1) {
+      interleave(order, out);
+    } else {
+      size_t a = 0;
+      while (a < order.size()) {
+        const int g = d.env_sdf[d.inst_env[tiles[order[a]].inst]];
+        size_t b = a;
+        while (b < order.size() && d.env_sdf[d.inst_env[tiles[order[b]].inst]] == g) ++b;
+        interleave(std::vector<int32_t>(order.begin() + a, order.begin() + b), out);
+        a = b;
+      }
     }
-    order.clear();
-    std::vector<size_t> pos((size_t)xcd, 0);
-    bool more = true;
-    while (more) {
-      more = false;
-      for (int s = 0; s < xcd; ++s)
-        if (pos[s] < seg[s].size()) {
-          order.push_back(seg[s][pos[s]++]);
-          more = true;
-        }
-    }
+    order.swap(out);
   }
   return TACSL_OK;
 }

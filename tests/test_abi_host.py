@@ -145,7 +145,7 @@ def _independent_tiles(sc, tile):
 
 
 @pytest.mark.parametrize("tile", [0, 64, 192, 1024])
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
 def test_worklist_covers_every_taxel_once(tile, order):
     sc = _uneven()
     w = api.build_worklist(sc, dict(block=64, tile_taxels=tile, order=order))
@@ -169,6 +169,17 @@ def test_xcd_order_groups_objects():
     # slots s with the same s % 8 run on the same XCD: few distinct objects each
     per_xcd = [len(set(sdf_of_tile[slots[x::8]].tolist())) for x in range(8)]
     assert max(per_xcd) <= 2, per_xcd
+    # object-major with per-XCD runs: objects appear one after the other, and
+    # within an object each XCD (slot % 8) gets a contiguous run of its tiles
+    w4 = api.build_worklist(sc, dict(order=4), xcd_count=8)
+    obj = sc.env_sdf[sc.inst_env[w4["inst"]]][w4["order"]]
+    assert np.all(np.diff(obj) >= 0)
+    for g in np.unique(obj):
+        tiles_g = w4["order"][obj == g]            # the object's tiles in slot order
+        rank = np.argsort(np.argsort(tiles_g))     # position in the object's own (instance-major) list
+        for x in range(8):
+            run = rank[x::8][:-1]                  # equal-cost segments: all rounds but the last are full
+            assert np.all(np.diff(run) == 1), (g, x, run)
     # longest-first order is non-increasing in tile size
     w2 = api.build_worklist(wl.make_uneven_small(), dict(order=2, tile_taxels=256))  # block 256
     sizes = w2["count"][w2["order"]]
@@ -177,7 +188,7 @@ def test_xcd_order_groups_objects():
 
 def test_bad_tunings_rejected():
     sc = _uneven()
-    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=4),
+    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=5),
                 dict(grid=-1)):
         with pytest.raises(_abi.TacslError) as ei:
             api.build_worklist(sc, bad)
