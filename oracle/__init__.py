@@ -62,6 +62,7 @@ def _load():
         lib.oracle_signature.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_footprint.argtypes = [P, P, ctypes.c_int, P]
         lib.oracle_footprint.restype = ctypes.c_int64
+        lib.oracle_depth_image.argtypes = [P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int]
         lib.oracle_contact_impulse.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double, P, P]
         _lib = lib
     return _lib
@@ -242,3 +243,29 @@ def observation(scene, ff, tmpl_bin, n_bins, scale=(1.0, 1.0, 1.0), clip=0.0, se
     if clip > 0:
         obs = np.clip(obs, -clip, clip)
     return obs
+
+
+class Camera(ctypes.Structure):
+    """Tactile camera: pixel (r, c) looks through the pad-plane point
+    (x0 + (c + 1/2) dx, y0 + (r + 1/2) dy, 0); pinhole at (0, 0, -cam_dist)
+    unless ortho; the gel spans z in [-gel, 0]."""
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("ortho", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("cam_dist", ctypes.c_double), ("gel", ctypes.c_double)]
+
+
+def depth_image(scene, state, cam, sel=None, nthreads=0):
+    """Tactile depth image per selected pad (Section III-B): z-distance from the
+    camera plane to the first point inside the gel where the object's trilinear
+    SDF is <= 0, else to the gel surface.  Returns (image, slope, phimin), each
+    FP64 [n_sel][rows][cols]; slope = d(phi)/dz at the hit (0 without one),
+    phimin = smallest phi sampled along the searched ray segment."""
+    if sel is None:
+        sel = np.arange(scene.n_inst, dtype=np.int32)
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    b = _Bound(scene, state)
+    shape = (sel.size, cam.rows, cam.cols)
+    img, sl, pm = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+    _load().oracle_depth_image(ctypes.byref(b.sc), ctypes.byref(b.st), ctypes.byref(cam), int(sel.size), _ptr(sel),
+                               _ptr(img), _ptr(sl), _ptr(pm), int(nthreads))
+    return img, sl, pm

@@ -527,6 +527,150 @@ int64_t oracle_footprint(const oracle_scene* sc, const oracle_state* st, int n_s
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Tactile depth image (Section III-B): a camera inside the sensor, behind the
+// gel, sees the indenting object.  Pixel (r, c) looks through the pad-plane
+// point P = (x0 + (c + 1/2) dx, y0 + (r + 1/2) dy, 0) (pad frame, +z towards
+// the object).  The ray is parametrized by its pad-frame height z: for a
+// pinhole at (0, 0, -D) its point at height z is P (z + D) / D in x, y;
+// for an orthographic camera it is (P_x, P_y, z).  The gel occupies
+// z in [-gel, 0].  The pixel reads the z-distance from the camera plane
+// z = -D to the first point of the ray inside the gel where the object's
+// (trilinear) SDF is <= 0, or to the gel surface z = 0 when there is none.
+// Outside the grid's node box the object is absent.
+//
+// Along the ray the grid coordinates are affine in z, so inside one cell the
+// trilinear field is a cubic in z.  The ray is walked cell by cell over the
+// part of [-gel, 0] inside the node box; in each cell the cubic is sampled
+// at 64 points and the first sign change is bisected to machine precision.
+// slope[] receives d(phi)/dz at the hit (0 without a hit; its size tells how
+// well the hit is conditioned), phimin[] the smallest sampled phi on the
+// searched segment (how close a ray without a hit came to the surface).
+// ---------------------------------------------------------------------------
+extern "C" {
+typedef struct {
+  int32_t rows, cols;
+  int32_t ortho;         // 1: rays parallel to +z; 0: pinhole at (0, 0, -cam_dist)
+  double x0, y0, dx, dy; // pixel grid on the pad plane (pad frame, metres)
+  double cam_dist;       // camera plane z = -cam_dist (>= gel)
+  double gel;            // gel thickness
+} oracle_camera;
+}
+
+struct RayCell {
+  double a[8];  // corner values, index dx + 2 dy + 4 dz
+};
+
+static double tri_at(const RayCell& rc, double tx, double ty, double tz) {
+  const double* a = rc.a;
+  double x00 = a[0] + (a[1] - a[0]) * tx, x10 = a[2] + (a[3] - a[2]) * tx;
+  double x01 = a[4] + (a[5] - a[4]) * tx, x11 = a[6] + (a[7] - a[6]) * tx;
+  double y0 = x00 + (x10 - x00) * ty, y1 = x01 + (x11 - x01) * ty;
+  return y0 + (y1 - y0) * tz;
+}
+
+extern "C" int oracle_depth_image(const oracle_scene* sc, const oracle_state* st, const oracle_camera* cam, int n_sel,
+                                  const int32_t* sel, double* image, double* slope, double* phimin, int nthreads) {
+  const int64_t npx = (int64_t)cam->rows * cam->cols;
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int s = 0; s < n_sel; ++s) {
+    Instance<double> I;
+    setup_instance<double>(*sc, *st, sel[s], I);
+    SDFView g{I.nx, I.ny, I.nz, I.phi};
+    const int n[3] = {I.nx, I.ny, I.nz};
+    const double D = cam->cam_dist;
+    for (int r = 0; r < cam->rows; ++r)
+      for (int c = 0; c < cam->cols; ++c) {
+        const int64_t q = (int64_t)s * npx + (int64_t)r * cam->cols + c;
+        const double px = cam->x0 + (c + 0.5) * cam->dx, py = cam->y0 + (r + 0.5) * cam->dy;
+        // ray point at height z (pad frame) and its grid coordinates u(z) = u0 + z uz
+        V3<double> X0 = v3<double>(px, py, 0.0);
+        V3<double> Xz = cam->ortho ? v3<double>(0.0, 0.0, 1.0) : v3<double>(px / D, py / D, 1.0);
+        V3<double> O0 = mulT(I.Ro, sub(add(mul(I.Rp, X0), I.tp), I.to));
+        V3<double> Oz = mulT(I.Ro, mul(I.Rp, Xz));
+        double u0[3] = {(O0.x - I.ox) / I.h, (O0.y - I.oy) / I.h, (O0.z - I.oz) / I.h};
+        double uz[3] = {Oz.x / I.h, Oz.y / I.h, Oz.z / I.h};
+        double zlo = -cam->gel, zhi = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          if (uz[a] == 0.0) {
+            if (!(u0[a] >= 0.0 && u0[a] <= n[a] - 1)) zlo = 1.0, zhi = 0.0;
+            continue;
+          }
+          double za = (0.0 - u0[a]) / uz[a], zb = (n[a] - 1 - u0[a]) / uz[a];
+          if (za > zb) std::swap(za, zb);
+          zlo = std::max(zlo, za);
+          zhi = std::min(zhi, zb);
+        }
+        double zhit = 0.0, sl = 0.0, pmin = INFINITY;
+        bool hit = false;
+        double z = zlo;
+        while (!hit && z < zhi) {
+          // end of the current cell along the ray: the next integer plane crossed
+          double znext = zhi;
+          for (int a = 0; a < 3; ++a) {
+            if (uz[a] == 0.0) continue;
+            const double ua = u0[a] + z * uz[a];
+            const double dir = uz[a] > 0 ? 1.0 : -1.0;
+            double plane = uz[a] > 0 ? std::floor(ua) + 1.0 : std::ceil(ua) - 1.0;
+            double zc = (plane - u0[a]) / uz[a];
+            // a start that rounds onto (or just before) a plane: take the plane after it
+            while (!(zc > z)) {
+              plane += dir;
+              zc = (plane - u0[a]) / uz[a];
+            }
+            if (zc < znext) znext = zc;
+          }
+          const double zm = 0.5 * (z + znext);
+          int cc[3];
+          for (int a = 0; a < 3; ++a) {
+            int f = (int)std::floor(u0[a] + zm * uz[a]);
+            cc[a] = std::min(std::max(f, 0), n[a] - 2);
+          }
+          RayCell rc;
+          for (int k = 0; k < 8; ++k) rc.a[k] = g.at(cc[0] + (k & 1), cc[1] + ((k >> 1) & 1), cc[2] + (k >> 2));
+          auto phi_at = [&](double zz) {
+            return tri_at(rc, u0[0] + zz * uz[0] - cc[0], u0[1] + zz * uz[1] - cc[1], u0[2] + zz * uz[2] - cc[2]);
+          };
+          const int K = 64;
+          double zp = z, fp = phi_at(z);
+          pmin = std::min(pmin, fp);
+          if (fp <= 0.0) {
+            hit = true;
+            zhit = z;
+          }
+          for (int k = 1; k <= K && !hit; ++k) {
+            double zk = z + (znext - z) * k / K;
+            double fk = phi_at(zk);
+            pmin = std::min(pmin, fk);
+            if (fk <= 0.0) {
+              double lo = zp, hi = zk;  // phi(lo) > 0 >= phi(hi)
+              for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (phi_at(mid) <= 0.0) hi = mid; else lo = mid;
+              }
+              hit = true;
+              zhit = hi;
+            }
+            zp = zk;
+            fp = fk;
+          }
+          if (hit) {
+            const double e = 1e-9 * I.h;
+            sl = (phi_at(std::min(zhit + e, znext)) - phi_at(std::max(zhit - e, z))) /
+                 (std::min(zhit + e, znext) - std::max(zhit - e, z));
+          }
+          z = znext;
+        }
+        image[q] = (hit ? zhit : 0.0) + D;
+        if (slope) slope[q] = hit ? sl : 0.0;
+        if (phimin) phimin[q] = std::isfinite(pmin) ? pmin : 0.0;
+      }
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Implicit soft-contact impulse (Section III-A, "Constraint Solution").
 // The Kelvin-Voigt contact force is applied as an implicit spring: the
 // impulse over a step satisfies the force law at the END of the step,
