@@ -318,6 +318,40 @@ def run_observation(args, torch, api, wl, sc, tun):
     return res
 
 
+def run_depth(args, torch, api, wl, sc):
+    """Tactile depth image of the roofline batch: every pad seen by an 80 x 60
+    pinhole camera 20 mm behind a 4 mm gel (16384 images per frame)."""
+    plan = api.Plan(sc)
+    rows, cols = 80, 60
+    plan.set_camera(rows, cols, -wl.PAD_W / 2, -wl.PAD_H / 2, wl.PAD_W / cols, wl.PAD_H / rows, 20e-3, 4e-3)
+    st = plan.state(sc.state())
+    status = torch.zeros(1, device=plan.device, dtype=torch.int32)
+    img = plan.depth_image(st, status=status)
+    for _ in range(args.warmup):
+        plan.depth_image(st, image=img, status=status)
+    reps = max(10, args.steps // 2)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        plan.depth_image(st, image=img, status=status)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    px = sc.n_inst * rows * cols
+    hit = float((img < 20e-3 - 1e-9).float().mean().item())
+    res = {"workload": "roofline batch, 80 x 60 pinhole camera per pad (20 mm behind a 4 mm gel)",
+           "pads": sc.n_inst, "pixels_per_frame": px, "ms_per_frame": ms, "wall_ms_per_frame": wall * 1e3 / reps,
+           "pixels_per_s": px / (ms * 1e-3), "env_frames_per_s": sc.n_env / (ms * 1e-3),
+           "pixels_on_object": hit, "step_limit_hit": bool(int(status.item()) & 0x8)}
+    log(f"depth image: {ms:.3f} ms/frame, {px / (ms * 1e-3):.3e} px/s, {hit:.3f} of pixels on the object")
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_impulse(args, torch, api, wl):
     """Batched implicit soft-contact impulse: per call 16 B read (eps, eps_dot,
     1/m, env) and 8 B written (lambda, dv) per contact, plus 8 B per
@@ -367,6 +401,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-impulse", action="store_true")
     ap.add_argument("--no-observation", action="store_true")
+    ap.add_argument("--no-depth", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--threads", type=int, default=16)
     ap.add_argument("--tuning", type=str, default=None,
@@ -381,6 +416,7 @@ def main():
         args.no_backward = True
         args.no_impulse = True
         args.no_observation = True
+        args.no_depth = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (environments shard "
               f"across GPUs without exchange; only the single-GPU shard is built here).", file=sys.stderr)
@@ -423,6 +459,9 @@ def main():
     backward = None
     if not args.no_backward:
         backward = run_backward(args, torch, api, wl)
+    depth = None
+    if not args.no_depth:
+        depth = run_depth(args, torch, api, wl, sc)
     impulse = None
     if not args.no_impulse:
         impulse = run_impulse(args, torch, api, wl)
@@ -440,7 +479,7 @@ def main():
                    "n_env": sc.n_env, "n_pads": sc.n_inst, "taxels_per_step": sc.n_taxels,
                    "contact_fraction": m["contact"], "tuning": m["tuning"], "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched, "differentiation": backward,
-        "contact_impulse": impulse, "observation": observation,
+        "contact_impulse": impulse, "observation": observation, "depth_image": depth,
     }
     print(json.dumps(line), flush=True)
 

@@ -70,6 +70,7 @@ typedef enum {
 #define TACSL_DEV_NONFINITE_POSE 0x1u /* a pose, twist or parameter is NaN/Inf: that pad outputs zeros */
 #define TACSL_DEV_ZERO_QUAT 0x2u      /* a quaternion has zero norm: that pad outputs zeros */
 #define TACSL_DEV_BAD_CONTACT 0x4u    /* tacsl_contact_impulse: an invalid contact (see there) got lambda = 0 */
+#define TACSL_DEV_DEPTH_CAPPED 0x8u   /* tacsl_depth_image: a ray hit the iteration limit; it reads the gel surface */
 
 /* Scene: everything that stays fixed across steps.  Read at plan creation.
  *   n_env   environments (>= 0); n_inst pads (instances, >= 0);
@@ -245,6 +246,42 @@ int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* t
  * tacsl_force_field; the observation is deterministic (fixed summation order). */
 int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, float* obs,
                               hipStream_t stream);
+
+/* Tactile camera for the depth image (Section III-B: a camera inside the
+ * sensor renders the depth of the indenting object).  Pad frame, +z towards
+ * the object; the gel fills z in [-gel, 0] and the camera sits behind it.
+ *   rows, cols  image size, 1..4096 each; row r, column c looks through the
+ *               pad-plane point (x0 + (c + 1/2) dx, y0 + (r + 1/2) dy, 0)
+ *   ortho       1: rays parallel to +z; 0: pinhole at (0, 0, -cam_dist)
+ *   dx, dy      pixel pitch on the pad plane (> 0), metres
+ *   cam_dist    distance of the camera plane behind the pad plane, >= gel
+ *   gel         gel thickness (> 0) */
+typedef struct {
+  int32_t rows, cols, ortho;
+  float x0, y0, dx, dy;
+  float cam_dist, gel;
+} tacsl_camera;
+
+/* Install (or with cam = NULL remove) the plan's tactile camera.  Host only;
+ * TACSL_ERR_RANGE for invalid values. */
+int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam);
+
+/* Tactile depth image of every pad: image (device float [n_inst][rows][cols])
+ * receives, per pixel, the distance along +z from the camera plane to the
+ * first point of the pixel's ray inside the gel where the object's trilinear
+ * SDF is <= 0, or cam_dist (the undeformed gel surface) when the ray meets no
+ * object inside the gel and the object's grid box.  An object reaching
+ * below the gel reads cam_dist - gel.  The ray advances cell by cell:
+ * sphere-tracing steps (with a per-grid bound on |grad phi|) where they
+ * leave the current cell, else an exact search of the rest of the cell (the
+ * field is a cubic along the ray, split at the roots of its derivative, the
+ * first sign change bisected).  A ray that needs more than 4096 iterations
+ * (more grid planes than that inside the gel) reads the gel surface and sets
+ * TACSL_DEV_DEPTH_CAPPED in *status (optional device word).  TACSL_ERR_STATE
+ * without a camera.  Asynchronous on
+ * `stream`, no allocation, capturable. */
+int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, uint32_t* status,
+                      hipStream_t stream);
 
 /* Reverse mode (hand-written adjoint with recomputation of the forward),
  * enqueued on `stream`; same asynchrony rules as tacsl_force_field. */

@@ -23,6 +23,7 @@ STATUS_NAMES = {
 DEV_NONFINITE_POSE = 0x1
 DEV_ZERO_QUAT = 0x2
 DEV_BAD_CONTACT = 0x4
+DEV_DEPTH_CAPPED = 0x8
 
 EXPORTS = [
     "tacsl_abi_version", "tacsl_status_string", "tacsl_validate_scene", "tacsl_build_worklist",
@@ -30,6 +31,7 @@ EXPORTS = [
     "tacsl_force_field", "tacsl_force_field_backward", "tacsl_graph_create", "tacsl_graph_launch",
     "tacsl_graph_destroy", "tacsl_plan_timer_start", "tacsl_plan_timer_read", "tacsl_plan_destroy",
     "tacsl_contact_impulse", "tacsl_plan_set_observation", "tacsl_force_field_observe",
+    "tacsl_plan_set_camera", "tacsl_depth_image",
 ]
 MAX_OBS_BINS = 256
 
@@ -60,6 +62,11 @@ class Outputs(ctypes.Structure):
 class Grads(ctypes.Structure):
     _fields_ = [("w_fn", P), ("w_ft", P), ("g_obj_pose", P), ("g_obj_twist", P),
                 ("g_params", P), ("status", P)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("rows", I32), ("cols", I32), ("ortho", I32), ("x0", ctypes.c_float), ("y0", ctypes.c_float),
+                ("dx", ctypes.c_float), ("dy", ctypes.c_float), ("cam_dist", ctypes.c_float), ("gel", ctypes.c_float)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -107,6 +114,8 @@ def load():
     lib.tacsl_plan_destroy.argtypes = [P]
     lib.tacsl_plan_set_observation.argtypes = [P, I32, P, P, ctypes.c_float]
     lib.tacsl_force_field_observe.argtypes = [P, P, P, P, P]
+    lib.tacsl_plan_set_camera.argtypes = [P, P]
+    lib.tacsl_depth_image.argtypes = [P, P, P, P, P]
     lib.tacsl_contact_impulse.argtypes = [I64, P, P, P, P, I32, P, ctypes.c_float, P, P, P, P]
     for name in EXPORTS:
         if name not in ("tacsl_status_string",):

@@ -131,6 +131,7 @@ class Plan:
         self.n_taxels = int(info.n_taxels)
         self._tmpl_T = int(self._hs.tmpl_offset[-1]) if self._hs.tmpl_offset.size else 0
         self.obs_bins = 0
+        self._cam = None
         self._graphs: List["SubstepGraph"] = []
 
     # -- inspection --------------------------------------------------------
@@ -265,6 +266,36 @@ class Plan:
         _abi.check(self._lib.tacsl_force_field_observe(self._plan, ctypes.byref(s), ctypes.byref(o), _ptr(obs),
                                                        _stream_handle(stream)), "tacsl_force_field_observe")
         return obs, out
+
+    def set_camera(self, rows: int, cols: int, x0: float, y0: float, dx: float, dy: float, cam_dist: float,
+                   gel: float, ortho: bool = False):
+        """Install the tactile camera (pad frame; see tacsl_camera)."""
+        cam = _abi.Camera(int(rows), int(cols), int(bool(ortho)), float(x0), float(y0), float(dx), float(dy),
+                          float(cam_dist), float(gel))
+        _abi.check(self._lib.tacsl_plan_set_camera(self._plan, ctypes.byref(cam)), "tacsl_plan_set_camera")
+        self._cam = cam
+
+    def clear_camera(self):
+        _abi.check(self._lib.tacsl_plan_set_camera(self._plan, None), "tacsl_plan_set_camera")
+        self._cam = None
+
+    def depth_image(self, st: Dict[str, torch.Tensor], image: Optional[torch.Tensor] = None,
+                    status: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Tactile depth image of every pad, float32 (n_inst, rows, cols)."""
+        self._check_state(st)
+        cam = getattr(self, "_cam", None)
+        if cam is None:
+            raise RuntimeError("no camera set on this plan (call set_camera first)")
+        shape = (self.n_inst, cam.rows, cam.cols)
+        if image is None:
+            image = torch.empty(shape, device=self.device, dtype=torch.float32)
+        if image.dtype != torch.float32 or not image.is_contiguous() or tuple(image.shape) != shape \
+                or image.device != self.device:
+            raise ValueError(f"image must be a contiguous float32 {shape} tensor on {self.device}")
+        s = self._state_struct(st)
+        _abi.check(self._lib.tacsl_depth_image(self._plan, ctypes.byref(s), _ptr(image), _ptr(status),
+                                               _stream_handle(stream)), "tacsl_depth_image")
+        return image
 
     def backward(self, st: Dict[str, torch.Tensor], w_fn: torch.Tensor, w_ft: torch.Tensor,
                  grads: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:

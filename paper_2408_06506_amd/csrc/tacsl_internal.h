@@ -30,6 +30,7 @@ struct InstStatic {
   uint32_t stride_y;    // bytes between consecutive y
   uint32_t stride_q;    // bytes between consecutive x-pairs
   float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
+  float lip;            // bound on |grad phi| of the trilinear field (edge slopes combined)
 };
 
 // Per-step per-pad record written by the prologue (FP64 math, FP32 store).
@@ -142,6 +143,22 @@ struct GradReduceArgs {
   int32_t n_env;
 };
 
+// Tactile depth image: per pad, pixels in 8 x 8 blocks (one wavefront each).
+struct DepthArgs {
+  const InstStatic* stat;
+  const InstXf* xf;
+  int32_t n_inst;
+  int32_t rows, cols, ortho;
+  float x0, y0, dx, dy;  // pixel grid on the pad plane
+  float cam_dist, gel;
+  int32_t blocks_x;        // 8 x 8 blocks per image row of blocks
+  int32_t blocks_per_pad;
+  float* image;            // [n_inst][rows][cols]
+  uint32_t* status;        // may be null
+};
+
+hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream);
+hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream);
 hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h,
                                uint32_t* bad_count, hipStream_t stream);
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream);

@@ -207,6 +207,9 @@ struct tacsl_plan_s {
   int32_t* d_queue = nullptr;
   int32_t* d_env_inst_begin = nullptr;
   int32_t* d_env_inst = nullptr;
+  // tactile camera (set by tacsl_plan_set_camera)
+  bool has_cam = false;
+  tacsl_camera cam{};
   // observation epilogue (set by tacsl_plan_set_observation)
   int32_t obs_n = 0;
   float obs_scale[3] = {1.f, 1.f, 1.f};
@@ -512,6 +515,31 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   dfree(d_bad);
   if (e != hipSuccess) return fail(TACSL_ERR_HIP);
   if (bad) return fail(TACSL_ERR_RANGE);
+  // per grid, a bound on |grad phi| of the trilinear field: inside a cell each
+  // partial derivative interpolates the cell's edge slopes along that axis
+  std::vector<float> lip((size_t)d.n_sdf, 0.f);
+  if (d.n_sdf > 0) {
+    uint32_t* d_m = nullptr;
+    if (dalloc(&d_m, (size_t)3 * d.n_sdf) != hipSuccess) return fail(TACSL_ERR_ALLOC);
+    std::vector<uint32_t> m((size_t)3 * d.n_sdf, 0u);
+    bool ok = hipMemset(d_m, 0, m.size() * sizeof(uint32_t)) == hipSuccess;
+    for (int g = 0; ok && g < d.n_sdf; ++g)
+      ok = tacsl::launch_grid_slopes(d.sdf_data + d.sdf_offset[g], d.sdf_dims[3 * g], d.sdf_dims[3 * g + 1],
+                                     d.sdf_dims[3 * g + 2], d_m + 3 * g, nullptr) == hipSuccess;
+    ok = ok && hipMemcpy(m.data(), d_m, m.size() * sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess;
+    dfree(d_m);
+    if (!ok) return fail(TACSL_ERR_HIP);
+    for (int g = 0; g < d.n_sdf; ++g) {
+      double acc = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        float v;
+        std::memcpy(&v, &m[3 * g + a], sizeof(float));
+        const double sl = (double)v / (double)d.sdf_spacing[g];
+        acc += sl * sl;
+      }
+      lip[g] = (float)std::max(std::sqrt(acc) * (1.0 + 1e-5), 1e-6);
+    }
+  }
 
   // static per-pad records
   std::vector<InstStatic> st((size_t)d.n_inst);
@@ -533,6 +561,7 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     s.oy = d.sdf_origin[3 * g + 1];
     s.oz = d.sdf_origin[3 * g + 2];
     s.h = d.sdf_spacing[g];
+    s.lip = lip[g];
   }
   // environments -> pads (ascending)
   std::vector<int32_t> eib((size_t)d.n_env + 1, 0), ei((size_t)d.n_inst);
@@ -667,6 +696,66 @@ int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const t
     if (rc != TACSL_OK) return rc;
   }
   return enqueue_forward(plan, state, out, stream, false, obs);
+}
+
+int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (!cam) {
+    plan->has_cam = false;
+    return TACSL_OK;
+  }
+  const tacsl_camera& c = *cam;
+  if (c.rows < 1 || c.rows > 4096 || c.cols < 1 || c.cols > 4096 || (c.ortho != 0 && c.ortho != 1))
+    return TACSL_ERR_RANGE;
+  const float f[] = {c.x0, c.y0, c.dx, c.dy, c.cam_dist, c.gel};
+  for (float v : f)
+    if (!std::isfinite(v)) return TACSL_ERR_RANGE;
+  if (!(c.dx > 0.f) || !(c.dy > 0.f) || !(c.gel > 0.f) || !(c.cam_dist >= c.gel)) return TACSL_ERR_RANGE;
+  plan->cam = c;
+  plan->has_cam = true;
+  return TACSL_OK;
+}
+
+int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, uint32_t* status,
+                      hipStream_t stream) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (!plan->has_cam) return TACSL_ERR_STATE;
+  int rc = check_state(plan, state);
+  if (rc != TACSL_OK) return rc;
+  if (plan->n_inst == 0) return TACSL_OK;
+  if (!image) return TACSL_ERR_NULL_ARG;
+  tacsl::PrologueArgs pa{};
+  pa.pad_pose = state->pad_pose;
+  pa.obj_pose = state->obj_pose;
+  pa.pad_twist = state->pad_twist;
+  pa.obj_twist = state->obj_twist;
+  pa.params = state->params;
+  pa.obj_pose_delta = state->obj_pose_delta;
+  pa.stat = plan->d_stat;
+  pa.xf = plan->d_xf;
+  pa.n_inst = plan->n_inst;
+  pa.status = status;
+  pa.queue = plan->d_queue;
+  if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+  const tacsl_camera& c = plan->cam;
+  tacsl::DepthArgs da{};
+  da.stat = plan->d_stat;
+  da.xf = plan->d_xf;
+  da.n_inst = plan->n_inst;
+  da.rows = c.rows;
+  da.cols = c.cols;
+  da.ortho = c.ortho;
+  da.x0 = c.x0;
+  da.y0 = c.y0;
+  da.dx = c.dx;
+  da.dy = c.dy;
+  da.cam_dist = c.cam_dist;
+  da.gel = c.gel;
+  da.blocks_x = (c.cols + 7) / 8;
+  da.blocks_per_pad = da.blocks_x * ((c.rows + 7) / 8);
+  da.image = image;
+  da.status = status;
+  return tacsl::launch_depth_image(da, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
 }
 
 int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* g,
