@@ -45,7 +45,8 @@ class _Scene(ctypes.Structure):
 class _State(ctypes.Structure):
     _fields_ = [("pad_pose", ctypes.c_void_p), ("obj_pose", ctypes.c_void_p),
                 ("pad_twist", ctypes.c_void_p), ("obj_twist", ctypes.c_void_p),
-                ("params", ctypes.c_void_p), ("obj_pose_delta", ctypes.c_void_p)]
+                ("params", ctypes.c_void_p), ("obj_pose_delta", ctypes.c_void_p),
+                ("normal_exponent", ctypes.c_double)]
 
 
 def _load():
@@ -95,7 +96,8 @@ class _Bound:
             _ptr(c(state["pad_pose"], np.float64)), _ptr(c(state["obj_pose"], np.float64)),
             _ptr(c(state["pad_twist"], np.float64)), _ptr(c(state["obj_twist"], np.float64)),
             _ptr(c(state["params"], np.float64)),
-            None if delta is None else _ptr(c(delta, np.float64)))
+            None if delta is None else _ptr(c(delta, np.float64)),
+            float(state.get("normal_exponent", 1.0)))
 
 
 def offsets(scene):
@@ -116,7 +118,8 @@ def force_field(scene, state, sel=None, nthreads=0, signature=False):
 
     ``state`` holds pad_pose, obj_pose, pad_twist, obj_twist, params and an
     optional obj_pose_delta, each widened to FP64 (pass the FP32 inputs of the
-    GPU path to compare like with like).
+    GPU path to compare like with like), and optionally normal_exponent (the
+    power p of the penetration in the normal law, 1 by default).
     """
     if sel is None:
         sel = np.arange(scene.n_inst, dtype=np.int32)

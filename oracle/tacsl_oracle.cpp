@@ -66,6 +66,13 @@ template <int N> Dual<N> sqrt(const Dual<N>& a) { Dual<N> r; r.v = std::sqrt(a.v
 template <int N> Dual<N> sin(const Dual<N>& a) { Dual<N> r; r.v = std::sin(a.v); double c = std::cos(a.v); for (int i = 0; i < N; ++i) r.d[i] = c * a.d[i]; return r; }
 template <int N> Dual<N> cos(const Dual<N>& a) { Dual<N> r; r.v = std::cos(a.v); double s = -std::sin(a.v); for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
 template <int N> Dual<N> fabs(const Dual<N>& a) { return a.v < 0 ? -a : a; }
+// a^p for a > 0 and a constant exponent p
+template <int N> Dual<N> powc(const Dual<N>& a, double p) {
+  Dual<N> r; r.v = std::pow(a.v, p); double d = p * std::pow(a.v, p - 1.0);
+  for (int i = 0; i < N; ++i) r.d[i] = d * a.d[i];
+  return r;
+}
+inline double powc(double a, double p) { return std::pow(a, p); }
 
 inline double val(double x) { return x; }
 template <int N> inline double val(const Dual<N>& x) { return x.v; }
@@ -168,6 +175,7 @@ typedef struct {
   const double* obj_twist;      // [n_env][6]
   const double* params;         // [n_env][4] k_n k_d k_t mu
   const double* obj_pose_delta; // [n_env][6] dt dtheta (may be NULL): R_o <- Exp(dtheta) R_o, t_o <- t_o + dt
+  double normal_exponent;       // p of the normal law (1: the law of Section III-C; see eval_taxel)
 } oracle_state;
 }
 
@@ -180,6 +188,7 @@ template <class S> struct Instance {
   V3<double> vp, wp;                // pad twist
   V3<S> vo, wo;                     // object twist
   S kn, kd, kt, mu;                 // contact parameters
+  double hc;                        // exponent of the penetration in the normal law (1: linear)
   // grid
   int nx, ny, nz;
   double ox, oy, oz, h;
@@ -265,9 +274,13 @@ static TaxelOut<S> eval_taxel(const Instance<S>& I, const V3<double>& xp) {
   V3<S> vpad = add(lift<S>(I.vp), lift<S>(cross(I.wp, sub(xw, I.tp))));
   V3<S> vobj = add(I.vo, cross(I.wo, sub(lift<S>(xw), I.to)));
   V3<S> xdot = mulT(Rp, sub(vpad, vobj));
-  // (8) normal force f_n = (-k_n + k_d d_dot) d n with d = phi.
+  // (8) normal force f_n = (-k_n + k_d d_dot) d n with d = phi.  With an
+  // exponent p != 1 the penetration -phi enters as (-phi)^p: the nonlinear
+  // (Hunt-Crossley) variant named in Section VII, damping still scaled by
+  // the same power of the penetration.
   S ddot = dot(n_p, xdot);
-  S s = (-I.kn + I.kd * ddot) * phi;
+  S dpow = I.hc == 1.0 ? phi : -powc(-phi, I.hc);
+  S s = (-I.kn + I.kd * ddot) * dpow;
   o.n = n_p;
   o.fn = scl(n_p, s);
   // (9) friction: f_t = -v_t/|v_t| min(k_t |v_t|, mu |f_n|).
@@ -311,6 +324,7 @@ static void setup_instance(const oracle_scene& sc, const oracle_state& st, int i
   I.wo = v3<S>(S(ot[3]), S(ot[4]), S(ot[5]));
   const double* p = st.params + 4 * (int64_t)e;
   I.kn = S(p[0]); I.kd = S(p[1]); I.kt = S(p[2]); I.mu = S(p[3]);
+  I.hc = st.normal_exponent > 0.0 ? st.normal_exponent : 1.0;
   I.nx = sc.sdf_dims[3 * sd]; I.ny = sc.sdf_dims[3 * sd + 1]; I.nz = sc.sdf_dims[3 * sd + 2];
   I.ox = sc.sdf_origin[3 * sd]; I.oy = sc.sdf_origin[3 * sd + 1]; I.oz = sc.sdf_origin[3 * sd + 2];
   I.h = sc.sdf_spacing[sd];
