@@ -318,6 +318,32 @@ def run_observation(args, torch, api, wl, sc, tun):
     return res
 
 
+def run_nonlinear_law(args, torch, api, wl, sc, tun):
+    """The roofline batch with the penetration to the power 1.5 in the normal
+    law (same tuning as the main leg): cost of the nonlinear variant."""
+    plan = api.Plan(sc, tun)
+    plan.set_normal_law(1.5)
+    st = plan.state(sc.state())
+    out = plan.new_outputs()
+    for _ in range(args.warmup):
+        plan.forward(st, out)
+    steps = max(10, args.steps // 2)
+    plan.timer_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(st, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = float(np.mean(plan.timer_read(steps)))
+    plan.close()
+    del out
+    torch.cuda.empty_cache()
+    log(f"normal law p=1.5: {wall * 1e3 / steps:.4f} ms/step, kernel {kms:.4f} ms")
+    return {"exponent": 1.5, "ms_per_step": wall * 1e3 / steps, "kernel_avg_ms": kms,
+            "taxel_evals_per_s": sc.n_taxels * steps / wall}
+
+
 def run_depth(args, torch, api, wl, sc):
     """Tactile depth image of the roofline batch: every pad seen by an 80 x 60
     pinhole camera 20 mm behind a 4 mm gel (16384 images per frame)."""
@@ -402,6 +428,7 @@ def main():
     ap.add_argument("--no-impulse", action="store_true")
     ap.add_argument("--no-observation", action="store_true")
     ap.add_argument("--no-depth", action="store_true")
+    ap.add_argument("--no-nonlinear", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--threads", type=int, default=16)
     ap.add_argument("--tuning", type=str, default=None,
@@ -417,6 +444,7 @@ def main():
         args.no_impulse = True
         args.no_observation = True
         args.no_depth = True
+        args.no_nonlinear = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (environments shard "
               f"across GPUs without exchange; only the single-GPU shard is built here).", file=sys.stderr)
@@ -443,6 +471,9 @@ def main():
     observation = None
     if not args.no_observation:
         observation = run_observation(args, torch, api, wl, sc, m["tuning"])
+    nonlinear = None
+    if not args.no_nonlinear:
+        nonlinear = run_nonlinear_law(args, torch, api, wl, sc, m["tuning"])
     roof = {"bound": "hbm", "achieved": m["achieved"] / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": m["achieved"] / HBM_PEAK, "traffic": traffic, "kernel": "k_force_fwd",
             "kernel_avg_ms": m["kernel_ms"], "algorithmic_bytes_per_launch": m["bytes"],
@@ -480,6 +511,7 @@ def main():
                    "contact_fraction": m["contact"], "tuning": m["tuning"], "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched, "differentiation": backward,
         "contact_impulse": impulse, "observation": observation, "depth_image": depth,
+        "nonlinear_normal_law": nonlinear,
     }
     print(json.dumps(line), flush=True)
 

@@ -247,6 +247,16 @@ int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* t
 int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, float* obs,
                               hipStream_t stream);
 
+/* Normal law of the plan: the penetration -phi enters the normal force as
+ * (-phi)^p, f_n = (k_n - k_d d_dot) (-phi)^p n (damping scaled by the same
+ * power), the nonlinear (Hunt-Crossley) variant named in Section VII; p = 1
+ * (the default) is the law of Section III-C.  k_n is then in N/m^p and k_d in
+ * N s/m^(p+1).  Applies to the forward, observation and adjoint passes (the
+ * adjoint does not differentiate with respect to p).  exponent in [1, 4],
+ * else TACSL_ERR_RANGE; TACSL_ERR_STATE while a graph of the plan exists
+ * (graphs keep the exponent they were captured with).  Host only. */
+int tacsl_plan_set_normal_law(tacsl_plan plan, float exponent);
+
 /* Tactile camera for the depth image (Section III-B: a camera inside the
  * sensor renders the depth of the indenting object).  Pad frame, +z towards
  * the object; the gel fills z in [-gel, 0] and the camera sits behind it.

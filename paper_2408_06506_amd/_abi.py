@@ -31,7 +31,7 @@ EXPORTS = [
     "tacsl_force_field", "tacsl_force_field_backward", "tacsl_graph_create", "tacsl_graph_launch",
     "tacsl_graph_destroy", "tacsl_plan_timer_start", "tacsl_plan_timer_read", "tacsl_plan_destroy",
     "tacsl_contact_impulse", "tacsl_plan_set_observation", "tacsl_force_field_observe",
-    "tacsl_plan_set_camera", "tacsl_depth_image",
+    "tacsl_plan_set_camera", "tacsl_depth_image", "tacsl_plan_set_normal_law",
 ]
 MAX_OBS_BINS = 256
 
@@ -115,6 +115,7 @@ def load():
     lib.tacsl_plan_set_observation.argtypes = [P, I32, P, P, ctypes.c_float]
     lib.tacsl_force_field_observe.argtypes = [P, P, P, P, P]
     lib.tacsl_plan_set_camera.argtypes = [P, P]
+    lib.tacsl_plan_set_normal_law.argtypes = [P, ctypes.c_float]
     lib.tacsl_depth_image.argtypes = [P, P, P, P, P]
     lib.tacsl_contact_impulse.argtypes = [I64, P, P, P, P, I32, P, ctypes.c_float, P, P, P, P]
     for name in EXPORTS:

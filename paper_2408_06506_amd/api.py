@@ -267,6 +267,10 @@ class Plan:
                                                        _stream_handle(stream)), "tacsl_force_field_observe")
         return obs, out
 
+    def set_normal_law(self, exponent: float = 1.0):
+        """Power p of the penetration in the normal law (1: linear)."""
+        _abi.check(self._lib.tacsl_plan_set_normal_law(self._plan, float(exponent)), "tacsl_plan_set_normal_law")
+
     def set_camera(self, rows: int, cols: int, x0: float, y0: float, dx: float, dy: float, cam_dist: float,
                    gel: float, ortho: bool = False):
         """Install the tactile camera (pad frame; see tacsl_camera)."""

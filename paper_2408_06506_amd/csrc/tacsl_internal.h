@@ -45,6 +45,7 @@ struct InstXf {
   float prm[4];  // k_n, k_d, k_t, mu
   float h;       // node spacing
   uint32_t ok;   // 0 when the pad's inputs were rejected (then A = 0, b = -1)
+  float hc;      // exponent p of the penetration in the normal law (1: linear)
 };
 
 // One unit of work: taxels [k0, k0 + count) of pad `inst`.
@@ -64,6 +65,7 @@ struct PrologueArgs {
   int32_t n_inst;
   uint32_t* status;  // may be null
   int32_t* queue;    // dynamic-schedule counter, reset to 0 here
+  float hc;          // normal-law exponent copied into every record
 };
 
 struct FwdArgs {

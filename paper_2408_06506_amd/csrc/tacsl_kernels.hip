@@ -214,6 +214,7 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     for (int k = 0; k < 4; ++k) x.prm[k] = 0.f;
     x.ok = 0;
   }
+  x.hc = a.hc;
   a.xf[i] = x;
   if (bits && a.status) atomicOr(a.status, bits);
 }
@@ -233,6 +234,7 @@ struct TaxelFwd {
   float n[3];
   float v[3];
   float dd, s;
+  float w, dw;  // penetration term of the normal law and its derivative in phi
   float vt[3];
   float vtn, cap;
   bool stick;
@@ -302,7 +304,17 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   f.v[1] = x.V[1] + fmaf(x.W[2], px, -x.W[0] * pz);
   f.v[2] = x.V[2] + fmaf(x.W[0], py, -x.W[1] * px);
   f.dd = fmaf(f.n[0], f.v[0], fmaf(f.n[1], f.v[1], f.n[2] * f.v[2]));
-  f.s = fmaf(x.prm[1], f.dd, -x.prm[0]) * f.phi;
+  // normal law s = (-k_n + k_d d_dot) w: w = phi (Section III-C), or with
+  // an exponent p != 1, w = -(-phi)^p (the nonlinear variant of Section VII)
+  f.w = f.phi;
+  f.dw = 1.f;
+  if (x.hc != 1.f) {
+    const float dl = -f.phi;
+    const float dp = exp2f(x.hc * log2f(dl));
+    f.w = -dp;
+    f.dw = x.hc * dp / dl;
+  }
+  f.s = fmaf(x.prm[1], f.dd, -x.prm[0]) * f.w;
   for (int a = 0; a < 3; ++a) {
     f.fn[a] = f.s * f.n[a];
     f.vt[a] = fmaf(-f.dd, f.n[a], f.v[a]);
@@ -830,11 +842,11 @@ __global__ __launch_bounds__(BLOCK) void k_force_bwd(
         vb[c] = vtb[c];
         nb[c] -= f.dd * vtb[c];
       }
-      // s = (-k_n + k_d d_dot) phi
-      const float knb = -f.phi * sb;
-      const float kdb = f.dd * f.phi * sb;
-      ddb += kd * f.phi * sb;
-      const float phib = (kd * f.dd - kn) * sb;
+      // s = (-k_n + k_d d_dot) w(phi)
+      const float knb = -f.w * sb;
+      const float kdb = f.dd * f.w * sb;
+      ddb += kd * f.w * sb;
+      const float phib = (kd * f.dd - kn) * sb * f.dw;
       // d_dot = n . x_dot
       for (int c = 0; c < 3; ++c) {
         nb[c] += ddb * f.v[c];

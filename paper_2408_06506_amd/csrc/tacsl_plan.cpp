@@ -207,6 +207,7 @@ struct tacsl_plan_s {
   int32_t* d_queue = nullptr;
   int32_t* d_env_inst_begin = nullptr;
   int32_t* d_env_inst = nullptr;
+  float hc = 1.f;  // normal-law exponent (tacsl_plan_set_normal_law)
   // tactile camera (set by tacsl_plan_set_camera)
   bool has_cam = false;
   tacsl_camera cam{};
@@ -327,6 +328,7 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   pa.n_inst = p->n_inst;
   pa.status = o->status;
   pa.queue = p->d_queue;
+  pa.hc = p->hc;
   if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
   const bool direct = p->n_tiles == p->n_inst;  // one tile per pad: tile id == pad id
   const bool fields = o->depth != nullptr;
@@ -698,6 +700,14 @@ int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const t
   return enqueue_forward(plan, state, out, stream, false, obs);
 }
 
+int tacsl_plan_set_normal_law(tacsl_plan plan, float exponent) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  if (!(exponent >= 1.f && exponent <= 4.f)) return TACSL_ERR_RANGE;
+  if (plan->live_graphs > 0) return TACSL_ERR_STATE;
+  plan->hc = exponent;
+  return TACSL_OK;
+}
+
 int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam) {
   if (!plan) return TACSL_ERR_NULL_ARG;
   if (!cam) {
@@ -736,6 +746,7 @@ int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, u
   pa.n_inst = plan->n_inst;
   pa.status = status;
   pa.queue = plan->d_queue;
+  pa.hc = plan->hc;
   if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
   const tacsl_camera& c = plan->cam;
   tacsl::DepthArgs da{};
@@ -780,6 +791,7 @@ int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const 
     pa.n_inst = plan->n_inst;
     pa.status = g->status;
     pa.queue = plan->d_queue;
+    pa.hc = plan->hc;
     if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
     tacsl::BwdArgs ba{};
     ba.tiles = plan->d_tiles;
