@@ -2,8 +2,9 @@
 
 Searches block size, tile size, schedule (one workgroup per tile, persistent
 static stride, persistent dynamic queue), persistent grid size and tile order
-(instance-major, XCD-aware object grouping, longest first, object-major) by
-timing the
+(instance-major, XCD-aware object grouping, longest first, object-major,
+object-major with per-XCD runs, and the same over pads in a spatial order
+rebuilt every call) by timing the
 forward call on the device with HIP events, and caches the winner per
 (GPU architecture, CU count, scene shape signature) in a JSON file
 (``TACSL_TUNE_CACHE`` or ``~/.cache/tacsl/tune.json``).
@@ -82,7 +83,7 @@ def candidates(plan, stage: int, base: Optional[dict] = None, schedules=(0, 1, 2
     if stage == 0:
         tiles = [0] + [t for t in (512, 1024, 2048, 4096) if t < cmax]
         for tile in tiles:
-            for order in (0, 1, 2, 3):
+            for order in (0, 1, 2, 3, 4, 5):
                 if 0 in schedules:
                     out.append(dict(block=256, tile_taxels=tile, schedule=0, grid=0, order=order))
                 for sch in (s for s in schedules if s in (1, 2)):

@@ -31,6 +31,7 @@ struct InstStatic {
   uint32_t stride_q;    // bytes between consecutive x-pairs
   float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
   float lip;            // bound on |grad phi| of the trilinear field (edge slopes combined)
+  int32_t gid;          // object grid index
 };
 
 // Per-step per-pad record written by the prologue (FP64 math, FP32 store).
@@ -66,6 +67,26 @@ struct PrologueArgs {
   uint32_t* status;  // may be null
   int32_t* queue;    // dynamic-schedule counter, reset to 0 here
   float hc;          // normal-law exponent copied into every record
+  // spatial order (tuning order 5), else null: per-pad spatial bin, and the
+  // pad's tile count added to its bin
+  uint32_t* sp_hist;                   // [n_sdf * kSpatialBins] (zero on entry)
+  int32_t* sp_bin;                     // [n_inst] bin of each pad
+  const int64_t* sp_inst_tile_begin;   // [n_inst + 1]
+};
+
+// Spatial execution order, rebuilt on the device every call: pads binned by
+// object grid and by the position of their origin in the grid (8 x 8 x 8
+// coarse cells in Morton order), each object's tiles in that order cut into
+// one contiguous run per XCD and interleaved (slot s runs on XCD s % 8).
+constexpr int kSpatialBins = 512;
+struct SpatialArgs {
+  int32_t n_inst, n_sdf, n_tiles;
+  uint32_t* hist;                  // [n_sdf * kSpatialBins] tiles per bin, left zeroed
+  uint32_t* cursor;                // [n_sdf * kSpatialBins] next free tile position of each bin
+  const int32_t* bin;              // [n_inst]
+  int32_t* grp_tile_begin;         // [n_sdf + 1]
+  const int64_t* inst_tile_begin;  // [n_inst + 1]
+  int32_t* order;                  // [n_tiles] out: slot -> tile id
 };
 
 struct FwdArgs {
@@ -159,6 +180,7 @@ struct DepthArgs {
   uint32_t* status;        // may be null
 };
 
+hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream);
 hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream);
 hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream);
 hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h,

@@ -217,7 +217,82 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
   x.hc = a.hc;
   a.xf[i] = x;
   if (bits && a.status) atomicOr(a.status, bits);
+  if (a.sp_hist) {
+    // coarse cell of the pad origin (u = b) in its grid, 8 per axis, Morton order
+    const int n3[3] = {st.nx, st.ny, st.nz};
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float cf = x.b[k] * 8.f / (float)(n3[k] - 1);
+      const uint32_t cb = (uint32_t)min(max((int)floorf(cf), 0), 7);
+#pragma unroll
+      for (int bit = 0; bit < 3; ++bit) m |= ((cb >> bit) & 1u) << (3 * bit + k);
+    }
+    const int bin = st.gid * kSpatialBins + (int)m;
+    a.sp_bin[i] = bin;
+    atomicAdd(a.sp_hist + bin, (uint32_t)(a.sp_inst_tile_begin[i + 1] - a.sp_inst_tile_begin[i]));
+  }
 }
+
+// Exclusive prefix of the bins' tile counts, in rounds of 1024 (one
+// workgroup): the next free position of each bin, the first tile of each
+// object grid, and the counts cleared for the next call.
+__global__ __launch_bounds__(1024) void k_sp_scan(const SpatialArgs a) {
+  __shared__ uint32_t lds[1024];
+  const int n = a.n_sdf * kSpatialBins;
+  const int t = threadIdx.x;
+  uint32_t carry = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int k = base + t;
+    const uint32_t v = k < n ? a.hist[k] : 0u;
+    lds[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t add = t >= o ? lds[t - o] : 0u;
+      __syncthreads();
+      lds[t] += add;
+      __syncthreads();
+    }
+    const uint32_t excl = carry + lds[t] - v;
+    if (k < n) {
+      a.cursor[k] = excl;
+      a.hist[k] = 0u;
+      if (k % kSpatialBins == 0) a.grp_tile_begin[k / kSpatialBins] = (int32_t)excl;
+    }
+    carry += lds[1023];
+    __syncthreads();
+  }
+  if (t == 0) a.grp_tile_begin[a.n_sdf] = (int32_t)carry;
+}
+
+// Each pad takes the next run of its bin's tile positions (any order within
+// a bin) and writes its tiles into the slots of the per-XCD interleave.
+__global__ __launch_bounds__(256) void k_sp_place(const SpatialArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n_inst) return;
+  const int bin = a.bin[i];
+  const int64_t t0 = a.inst_tile_begin[i];
+  const int cnt = (int)(a.inst_tile_begin[i + 1] - t0);
+  const int pos = (int)atomicAdd(a.cursor + bin, (uint32_t)cnt);
+  const int g = bin / kSpatialBins;
+  const int A = a.grp_tile_begin[g], n = a.grp_tile_begin[g + 1] - A;
+  const int q = n >> 3, r = n & 7;
+  for (int k = 0; k < cnt; ++k) {
+    const int jr = pos + k - A;  // rank in the object's spatially ordered tiles
+    int seg, off;
+    if (jr < r * (q + 1)) {
+      seg = jr / (q + 1);
+      off = jr - seg * (q + 1);
+    } else {
+      const int j2 = jr - r * (q + 1);
+      seg = r + j2 / q;
+      off = j2 - (seg - r) * q;
+    }
+    const int slot = A + (off < q ? off * 8 + seg : 8 * q + seg);
+    if (slot >= 0 && slot < a.n_tiles) a.order[slot] = (int32_t)(t0 + k);  // always true when counts agree
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 // Per-taxel forward (shared by the forward and the adjoint kernels).
@@ -1031,6 +1106,13 @@ hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t str
     case kFields | kObserve: return launch_forward_mode<kFields | kObserve>(a, block, grid, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream) {
+  if (a.n_inst == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(1024), 0, stream, a);
+  hipLaunchKernelGGL(k_sp_place, dim3((unsigned)((a.n_inst + 255) / 256)), dim3(256), 0, stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream) {

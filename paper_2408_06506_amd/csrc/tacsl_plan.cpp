@@ -78,7 +78,7 @@ int resolve_tuning(const tacsl_tuning* in, int cu_count, tacsl_tuning* out) {
   if (t.tile_taxels < 0 || (t.tile_taxels > 0 && t.tile_taxels < 64) || t.tile_taxels > kMaxTemplate)
     return TACSL_ERR_RANGE;
   if (t.schedule < 0 || t.schedule > 2) return TACSL_ERR_RANGE;
-  if (t.order < 0 || t.order > 4) return TACSL_ERR_RANGE;
+  if (t.order < 0 || t.order > 5) return TACSL_ERR_RANGE;
   if (t.grid < 0) return TACSL_ERR_RANGE;
   if (t.grid == 0) t.grid = std::max(1, cu_count) * 8;
   *out = t;
@@ -116,12 +116,14 @@ int make_worklist(const tacsl_scene_desc& d, const tacsl_tuning& t, int xcd, std
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
       return d.env_sdf[d.inst_env[tiles[a].inst]] < d.env_sdf[d.inst_env[tiles[b].inst]];
     });
-  } else if ((t.order == 1 || t.order == 4) && n > 0) {
+  } else if ((t.order == 1 || t.order == 4 || t.order == 5) && n > 0) {
     // group by object grid.  Order 1: cut the whole list into xcd contiguous
     // segments of equal cost, interleaved so that slot s runs on XCD s % xcd
     // while segments last.  Order 4: the same per object grid, one object
     // after the other (object-major for the memory-side cache, and each XCD
-    // on a contiguous run of the object's pads for its own L2).
+    // on a contiguous run of the object's pads for its own L2).  Order 5
+    // starts from order 4 and is rebuilt on the device every call with the
+    // pads in spatial order.
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
       return d.env_sdf[d.inst_env[tiles[a].inst]] < d.env_sdf[d.inst_env[tiles[b].inst]];
     });
@@ -219,6 +221,11 @@ struct tacsl_plan_s {
   float* d_obs_icnt = nullptr;       // [n_tmpl][obs_n]
   int32_t* d_obs_inst_tmpl = nullptr;  // [n_inst]
   float* d_obs_partial = nullptr;    // [n_tiles][obs_n][3]
+  // spatial order (order 5)
+  uint32_t* d_sp_hist = nullptr;
+  uint32_t* d_sp_cursor = nullptr;
+  int32_t* d_sp_bin = nullptr;
+  int32_t* d_sp_grp_tile = nullptr;
   int64_t n_tiles = 0;
   int64_t ws_bytes = 0;
   int live_graphs = 0;
@@ -256,6 +263,10 @@ struct tacsl_plan_s {
     dfree(d_partial);
     dfree(d_bpartial);
     dfree(d_obs_partial);
+    dfree(d_sp_hist);
+    dfree(d_sp_cursor);
+    dfree(d_sp_bin);
+    dfree(d_sp_grp_tile);
   }
   void free_observation() {
     dfree(d_obs_bin);
@@ -302,6 +313,16 @@ int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
     p->free_worklist();
     return TACSL_ERR_ALLOC;
   }
+  if (t.order == 5) {
+    const size_t nb = (size_t)tacsl::kSpatialBins * std::max(p->n_sdf, 1);
+    const size_t ni = (size_t)p->n_inst;
+    if (dalloc(&p->d_sp_hist, nb) != hipSuccess || dalloc(&p->d_sp_cursor, nb) != hipSuccess ||
+        dalloc(&p->d_sp_bin, ni) != hipSuccess || dalloc(&p->d_sp_grp_tile, (size_t)p->n_sdf + 1) != hipSuccess) {
+      p->free_worklist();
+      return TACSL_ERR_ALLOC;
+    }
+    if (hipMemset(p->d_sp_hist, 0, nb * sizeof(uint32_t)) != hipSuccess) return TACSL_ERR_HIP;
+  }
   if (n > 0 && (hipMemcpy(p->d_tiles, tiles.data(), n * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
                 hipMemcpy(p->d_order, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess))
     return TACSL_ERR_HIP;
@@ -311,6 +332,23 @@ int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
   p->n_tiles = (int64_t)n;
   p->tun = t;
   return TACSL_OK;
+}
+
+// Spatial order (order 5): the prologue has binned the pads; rebuild the
+// slot -> tile map for this call.
+int enqueue_spatial(tacsl_plan p, hipStream_t stream) {
+  if (p->tun.order != 5) return TACSL_OK;
+  tacsl::SpatialArgs sa{};
+  sa.n_inst = p->n_inst;
+  sa.n_sdf = p->n_sdf;
+  sa.n_tiles = (int32_t)p->n_tiles;
+  sa.hist = p->d_sp_hist;
+  sa.cursor = p->d_sp_cursor;
+  sa.bin = p->d_sp_bin;
+  sa.grp_tile_begin = p->d_sp_grp_tile;
+  sa.inst_tile_begin = p->d_inst_tile_begin;
+  sa.order = p->d_order;
+  return tacsl::launch_spatial_order(sa, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
 }
 
 int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, hipStream_t stream,
@@ -329,7 +367,14 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   pa.status = o->status;
   pa.queue = p->d_queue;
   pa.hc = p->hc;
+  if (p->tun.order == 5) {
+    pa.sp_hist = p->d_sp_hist;
+    pa.sp_bin = p->d_sp_bin;
+    pa.sp_inst_tile_begin = p->d_inst_tile_begin;
+  }
   if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+  int src = enqueue_spatial(p, stream);
+  if (src != TACSL_OK) return src;
   const bool direct = p->n_tiles == p->n_inst;  // one tile per pad: tile id == pad id
   const bool fields = o->depth != nullptr;
   tacsl::FwdArgs fa{};
@@ -564,6 +609,7 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     s.oz = d.sdf_origin[3 * g + 2];
     s.h = d.sdf_spacing[g];
     s.lip = lip[g];
+    s.gid = g;
   }
   // environments -> pads (ascending)
   std::vector<int32_t> eib((size_t)d.n_env + 1, 0), ei((size_t)d.n_inst);
@@ -792,7 +838,14 @@ int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const 
     pa.status = g->status;
     pa.queue = plan->d_queue;
     pa.hc = plan->hc;
+    if (plan->tun.order == 5) {
+      pa.sp_hist = plan->d_sp_hist;
+      pa.sp_bin = plan->d_sp_bin;
+      pa.sp_inst_tile_begin = plan->d_inst_tile_begin;
+    }
     if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+    rc = enqueue_spatial(plan, stream);
+    if (rc != TACSL_OK) return rc;
     tacsl::BwdArgs ba{};
     ba.tiles = plan->d_tiles;
     ba.order = plan->d_order;

@@ -145,7 +145,7 @@ def _independent_tiles(sc, tile):
 
 
 @pytest.mark.parametrize("tile", [0, 64, 192, 1024])
-@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4, 5])
 def test_worklist_covers_every_taxel_once(tile, order):
     sc = _uneven()
     w = api.build_worklist(sc, dict(block=64, tile_taxels=tile, order=order))
@@ -188,7 +188,7 @@ def test_xcd_order_groups_objects():
 
 def test_bad_tunings_rejected():
     sc = _uneven()
-    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=5),
+    for bad in (dict(block=96), dict(block=1024), dict(tile_taxels=10), dict(schedule=3), dict(order=6),
                 dict(grid=-1)):
         with pytest.raises(_abi.TacslError) as ei:
             api.build_worklist(sc, bad)
