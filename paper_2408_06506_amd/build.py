@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtacsl.so")
 SOURCES = [os.path.join(CSRC, "tacsl_plan.cpp"), os.path.join(CSRC, "tacsl_kernels.hip"),
-           os.path.join(CSRC, "tacsl_impulse.hip")]
+           os.path.join(CSRC, "tacsl_impulse.hip"), os.path.join(CSRC, "tacsl_depth.hip")]
 ARCH = "gfx950"
 
 

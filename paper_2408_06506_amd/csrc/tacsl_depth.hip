@@ -1,0 +1,276 @@
+// Tactile depth image kernels of libtacsl for gfx950 (MI355X), and the
+// per-grid Lipschitz bound the ray march relies on.
+#include <hip/hip_runtime.h>
+
+#include "tacsl.h"
+#include "tacsl_device.h"
+#include "tacsl_internal.h"
+
+namespace tacsl {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Tactile depth image (Section III-B).  A camera behind the gel looks along
+// +z of the pad frame; pixel (r, c) looks through the pad-plane point
+// P = (x0 + (c + 1/2) dx, y0 + (r + 1/2) dy, 0), from a pinhole at
+// (0, 0, -cam_dist) or along +z (orthographic).  Parametrized by its height
+// z, the ray is X(z) = P + z (P_x / D, P_y / D, 1) (pinhole) or P + z e_z, so
+// its grid coordinates are affine in z: u(z) = u0 + z uz.  The pixel reads
+// cam_dist + the height of the first point of [-gel, 0] (clipped to the node
+// box) where the trilinear phi <= 0, or cam_dist (the gel surface).
+//
+// The ray advances cell by cell.  Far from the surface it takes sphere-tracing
+// steps: with |grad phi| <= lip (per grid) and s = |dX/dz|, a step of
+// phi / (lip s) cannot pass the surface, and it is taken whenever it reaches
+// past the current cell.  Otherwise the rest of the cell is searched exactly:
+// along the ray the trilinear field is a cubic in z, monotone between the
+// roots of its derivative, so its sign at those points and at the cell exit
+// brackets the first root, which is bisected with the direct trilinear form.
+// Every iteration moves past at least one grid plane, so the work per ray is
+// bounded by the planes it crosses.
+// ---------------------------------------------------------------------------
+constexpr int kDepthMaxIter = 4096;
+
+__device__ __forceinline__ float load_phi(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+struct RayCell {
+  int cx, cy, cz;
+  float a[8];  // corner phi, index dx + 2 dy + 4 dz
+};
+
+__device__ __forceinline__ void ray_cell(const InstStatic& st, __amdgpu_buffer_rsrc_t rs, RayCell& rc, float ux,
+                                         float uy, float uz) {
+  // clamped on both sides: points on the box faces, and rounding just outside
+  const int cx = min(max((int)floorf(ux), 0), st.nx - 2);
+  const int cy = min(max((int)floorf(uy), 0), st.ny - 2);
+  const int cz = min(max((int)floorf(uz), 0), st.nz - 2);
+  if (cx == rc.cx && cy == rc.cy && cz == rc.cz) return;
+  rc.cx = cx;
+  rc.cy = cy;
+  rc.cz = cz;
+  const uint32_t yz = __umul24((uint32_t)cy, st.stride_y) + (uint32_t)cz * 32u;
+  const uint32_t x0 = (uint32_t)cx, x1 = x0 + 1u;
+  const uint32_t o0 = __umul24(x0 >> 1, st.stride_q) + (x0 & 1u) * 16u + yz;
+  const uint32_t o1 = __umul24(x1 >> 1, st.stride_q) + (x1 & 1u) * 16u + yz;
+  const uint32_t sy = st.stride_y;
+  rc.a[0] = load_phi(rs, o0, 0u);
+  rc.a[1] = load_phi(rs, o1, 0u);
+  rc.a[2] = load_phi(rs, o0, sy);
+  rc.a[3] = load_phi(rs, o1, sy);
+  rc.a[4] = load_phi(rs, o0 + 32u, 0u);
+  rc.a[5] = load_phi(rs, o1 + 32u, 0u);
+  rc.a[6] = load_phi(rs, o0 + 32u, sy);
+  rc.a[7] = load_phi(rs, o1 + 32u, sy);
+}
+
+__device__ __forceinline__ float cell_tri(const RayCell& rc, float tx, float ty, float tz) {
+  return tri(rc.a[0], rc.a[1], rc.a[2], rc.a[3], rc.a[4], rc.a[5], rc.a[6], rc.a[7], tx, ty, tz);
+}
+
+// Height of the next grid plane of one axis strictly above z.
+__device__ __forceinline__ float next_plane(float u0, float uz, float z) {
+  if (uz == 0.f) return INFINITY;
+  const float dir = uz > 0.f ? 1.f : -1.f;
+  const float ua = fmaf(z, uz, u0);
+  float plane = uz > 0.f ? floorf(ua) + 1.f : ceilf(ua) - 1.f;
+  float zc = (plane - u0) / uz;
+  for (int k = 0; k < 3 && !(zc > z); ++k) {
+    plane += dir;
+    zc = (plane - u0) / uz;
+  }
+  return zc > z ? zc : z + fabsf(1.f / uz);
+}
+
+// First root of the field on the ray segment [z, z + len] inside cell rc,
+// given t = p + q tau (tau = height above z).  Returns tau or -1.
+__device__ __forceinline__ float cell_first_root(const RayCell& rc, const float p[3], const float q[3], float len) {
+  const float* a = rc.a;
+  const float kx = a[1] - a[0], ky = a[2] - a[0], kz = a[4] - a[0];
+  const float kxy = a[3] - a[2] - a[1] + a[0];
+  const float kxz = a[5] - a[4] - a[1] + a[0];
+  const float kyz = a[6] - a[4] - a[2] + a[0];
+  const float kxyz = a[7] - a[6] - a[5] + a[4] - a[3] + a[2] + a[1] - a[0];
+  // phi(tau) = c0 + c1 tau + c2 tau^2 + c3 tau^3 (c0 not needed)
+  const float gx = kx + kxy * p[1] + kxz * p[2] + kxyz * p[1] * p[2];
+  const float gy = ky + kxy * p[0] + kyz * p[2] + kxyz * p[0] * p[2];
+  const float gz = kz + kxz * p[0] + kyz * p[1] + kxyz * p[0] * p[1];
+  const float c1 = gx * q[0] + gy * q[1] + gz * q[2];
+  const float c2 = (kxy + kxyz * p[2]) * q[0] * q[1] + (kxz + kxyz * p[1]) * q[0] * q[2] +
+                   (kyz + kxyz * p[0]) * q[1] * q[2];
+  const float c3 = kxyz * q[0] * q[1] * q[2];
+  // critical points: 3 c3 tau^2 + 2 c2 tau + c1 = 0 (stable quadratic roots)
+  float t1 = INFINITY, t2 = INFINITY;
+  const float A = 3.f * c3, B = 2.f * c2, C = c1;
+  if (A == 0.f) {
+    if (B != 0.f) t1 = -C / B;
+  } else {
+    const float disc = B * B - 4.f * A * C;
+    if (disc >= 0.f) {
+      const float qq = -0.5f * (B + copysignf(sqrtf(disc), B));
+      t1 = qq / A;
+      t2 = qq != 0.f ? C / qq : INFINITY;
+    }
+  }
+  if (t2 < t1) {
+    const float t = t1;
+    t1 = t2;
+    t2 = t;
+  }
+  float pts[3] = {t1, t2, len};
+  float lo = 0.f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float tj = pts[j];
+    if (!(tj > lo && tj <= len)) continue;  // outside the segment (or NaN)
+    if (cell_tri(rc, fmaf(tj, q[0], p[0]), fmaf(tj, q[1], p[1]), fmaf(tj, q[2], p[2])) <= 0.f) {
+      float hi = tj;  // phi(lo) > 0 >= phi(hi), monotone in between
+      for (int k = 0; k < 30; ++k) {
+        const float mid = 0.5f * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (cell_tri(rc, fmaf(mid, q[0], p[0]), fmaf(mid, q[1], p[1]), fmaf(mid, q[2], p[2])) <= 0.f)
+          hi = mid;
+        else
+          lo = mid;
+      }
+      return hi;
+    }
+    lo = tj;
+  }
+  return -1.f;
+}
+
+__global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t blk = (int64_t)blockIdx.x * 4 + wave;  // one 8 x 8 pixel block per wavefront
+  const int i = __builtin_amdgcn_readfirstlane((int)(blk / a.blocks_per_pad));
+  if (i >= a.n_inst) return;
+  const int b = (int)(blk - (int64_t)i * a.blocks_per_pad);
+  const int br = b / a.blocks_x, bc = b - br * a.blocks_x;
+  const int r = br * 8 + (lane >> 3), c = bc * 8 + (lane & 7);
+  if (r >= a.rows || c >= a.cols) return;
+  const InstStatic st = a.stat[i];
+  const InstXf x = a.xf[i];
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
+  const float px = fmaf((float)c + 0.5f, a.dx, a.x0), py = fmaf((float)r + 0.5f, a.dy, a.y0);
+  const float ex = a.ortho ? 0.f : px / a.cam_dist, ey = a.ortho ? 0.f : py / a.cam_dist;
+  const float u0[3] = {fmaf(x.A[0], px, fmaf(x.A[1], py, x.b[0])), fmaf(x.A[3], px, fmaf(x.A[4], py, x.b[1])),
+                       fmaf(x.A[6], px, fmaf(x.A[7], py, x.b[2]))};
+  const float uz[3] = {fmaf(x.A[0], ex, fmaf(x.A[1], ey, x.A[2])), fmaf(x.A[3], ex, fmaf(x.A[4], ey, x.A[5])),
+                       fmaf(x.A[6], ex, fmaf(x.A[7], ey, x.A[8]))};
+  float zlo = -a.gel, zhi = 0.f;
+  const int n[3] = {st.nx, st.ny, st.nz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float n1 = (float)(n[k] - 1);
+    if (uz[k] == 0.f) {
+      if (!(u0[k] >= 0.f && u0[k] <= n1)) zhi = -INFINITY;
+      continue;
+    }
+    const float za = -u0[k] / uz[k], zb = (n1 - u0[k]) / uz[k];
+    zlo = fmaxf(zlo, fminf(za, zb));
+    zhi = fminf(zhi, fmaxf(za, zb));
+  }
+  bool hit = false, capped = false;
+  float zh = 0.f;
+  if (zlo <= zhi) {
+    RayCell rc;
+    rc.cx = -1;
+    rc.cy = -1;
+    rc.cz = -1;
+    const float inv_ls = 1.f / (st.lip * sqrtf(fmaf(ex, ex, fmaf(ey, ey, 1.f))));
+    float z = zlo;
+    float u[3] = {fmaf(z, uz[0], u0[0]), fmaf(z, uz[1], u0[1]), fmaf(z, uz[2], u0[2])};
+    ray_cell(st, rs, rc, u[0], u[1], u[2]);
+    float phi = cell_tri(rc, u[0] - (float)rc.cx, u[1] - (float)rc.cy, u[2] - (float)rc.cz);
+    if (phi <= 0.f) {
+      hit = true;
+      zh = z;
+    } else {
+      int it = 0;
+      for (; it < kDepthMaxIter; ++it) {
+        const float ze = fminf(fminf(next_plane(u0[0], uz[0], z), next_plane(u0[1], uz[1], z)),
+                               next_plane(u0[2], uz[2], z));
+        const float zend = fminf(ze, zhi);
+        const float zs = z + phi * inv_ls;
+        if (zs >= zend) {  // a safe step that leaves the cell
+          if (zs >= zhi) break;
+          z = zs;
+          u[0] = fmaf(z, uz[0], u0[0]);
+          u[1] = fmaf(z, uz[1], u0[1]);
+          u[2] = fmaf(z, uz[2], u0[2]);
+          ray_cell(st, rs, rc, u[0], u[1], u[2]);
+          phi = cell_tri(rc, u[0] - (float)rc.cx, u[1] - (float)rc.cy, u[2] - (float)rc.cz);
+          if (phi <= 0.f) {  // only by rounding at the step's end
+            hit = true;
+            zh = z;
+            break;
+          }
+          continue;
+        }
+        // the rest of this cell, exactly; the cell is the one holding the open segment
+        const float zm = 0.5f * (z + zend);
+        ray_cell(st, rs, rc, fmaf(zm, uz[0], u0[0]), fmaf(zm, uz[1], u0[1]), fmaf(zm, uz[2], u0[2]));
+        const float p[3] = {fmaf(z, uz[0], u0[0]) - (float)rc.cx, fmaf(z, uz[1], u0[1]) - (float)rc.cy,
+                            fmaf(z, uz[2], u0[2]) - (float)rc.cz};
+        const float tau = cell_first_root(rc, p, uz, zend - z);
+        if (tau >= 0.f) {
+          hit = true;
+          zh = z + tau;
+          break;
+        }
+        if (zend >= zhi) break;
+        phi = cell_tri(rc, fmaf(zend - z, uz[0], p[0]), fmaf(zend - z, uz[1], p[1]), fmaf(zend - z, uz[2], p[2]));
+        z = zend;
+      }
+      capped = it >= kDepthMaxIter;
+    }
+  }
+  if (capped && a.status) atomicOr(a.status, TACSL_DEV_DEPTH_CAPPED);
+  __builtin_nontemporal_store((hit ? zh : 0.f) + a.cam_dist,
+                              a.image + (int64_t)i * a.rows * a.cols + (int64_t)r * a.cols + c);
+}
+
+// Largest node-to-node difference along each axis (|phi| units), for the
+// Lipschitz bound of the trilinear field.  max3 holds float bits (>= 0).
+__global__ __launch_bounds__(256) void k_grid_slopes(const float* __restrict__ phi, int nx, int ny, int nz,
+                                                     uint32_t* __restrict__ max3) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  float m[3] = {0.f, 0.f, 0.f};
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+    const int i = (int)(q % nx);
+    const int j = (int)((q / nx) % ny);
+    const int k = (int)(q / ((int64_t)nx * ny));
+    const float v = phi[q];
+    if (i + 1 < nx) m[0] = fmaxf(m[0], fabsf(phi[q + 1] - v));
+    if (j + 1 < ny) m[1] = fmaxf(m[1], fabsf(phi[q + nx] - v));
+    if (k + 1 < nz) m[2] = fmaxf(m[2], fabsf(phi[q + (int64_t)nx * ny] - v));
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    float v = m[d];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(max3 + d, __float_as_uint(v));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_grid_slopes, dim3((unsigned)blocks), dim3(256), 0, stream, phi, nx, ny, nz, max3);
+  return hipGetLastError();
+}
+
+hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream) {
+  const int64_t blocks = (int64_t)a.n_inst * a.blocks_per_pad;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_depth_image, dim3((unsigned)((blocks + 3) / 4)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace tacsl

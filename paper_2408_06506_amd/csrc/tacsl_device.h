@@ -1,0 +1,53 @@
+// Device helpers shared by the kernel sources of libtacsl (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tacsl {
+namespace {
+
+constexpr int kBufferFlags = 0x00020000;  // raw 32-bit dword access, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float4* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(p), (short)0, (int)bytes, kBufferFlags);
+}
+
+// One node record: per-lane byte offset + uniform (scalar) byte offset.
+__device__ __forceinline__ float4 load_node(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Element k of a row whose base is uniform; k * 4 < 2^32 (tiles hold < 2^30 taxels).
+__device__ __forceinline__ float at(const float* base, uint32_t k) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (k << 2));
+}
+// Outputs stream out once per step: non-temporal stores keep them from
+// evicting SDF lines from L2 and the memory-side cache.
+__device__ __forceinline__ void put(float* base, uint32_t k, float v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (k << 2)));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Trilinear interpolation of corner values (index dx + 2 dy + 4 dz).
+__device__ __forceinline__ float tri(float c0, float c1, float c2, float c3, float c4, float c5, float c6, float c7,
+                                     float tx, float ty, float tz) {
+  const float a0 = lerp(c0, c1, tx), a1 = lerp(c2, c3, tx), a2 = lerp(c4, c5, tx), a3 = lerp(c6, c7, tx);
+  return lerp(lerp(a0, a1, ty), lerp(a2, a3, ty), tz);
+}
+
+}  // namespace
+}  // namespace tacsl
