@@ -46,7 +46,8 @@ FOOTPRINT = os.path.join(ROOT, "tests", "golden", "sdf_footprint.json")
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_force_fwd_roofline_8192x2x80x100_256.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_06506_amd", "csrc", f) for f in ("tacsl_kernels.hip", "tacsl_internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_06506_amd", "csrc", f)
+                  for f in ("tacsl_kernels.hip", "tacsl_device.h", "tacsl_internal.h")]
 
 
 def measured_traffic(tuning):
@@ -280,10 +281,11 @@ def run_backward(args, torch, api, wl):
 def run_observation(args, torch, api, wl, sc, tun):
     """Fused observation epilogue on the roofline batch (14 x 10 bins x 3
     channels per pad): observation only (no per-taxel stores) and observation
-    with the per-taxel fields, same tuning as the main leg.  Algorithmic bytes
+    with the per-taxel fields, the main leg's tuning with one tile per pad.  Algorithmic bytes
     of the observation-only pass: the stencil footprint, the template and bin
     map, state in, wrench and observation out."""
-    plan = api.Plan(sc, tun)
+    # one tile per pad: the pooled partials are then one row per pad
+    plan = api.Plan(sc, dict(tun, tile_taxels=0))
     bins = wl.scene_observation_bins(sc)
     plan.set_observation(bins, 140, scale=(1.0, 1.0, 1.0))
     st = plan.state(sc.state())
