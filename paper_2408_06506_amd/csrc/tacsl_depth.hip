@@ -236,16 +236,18 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
 // Lipschitz bound of the trilinear field.  max3 holds float bits (>= 0).
 __global__ __launch_bounds__(256) void k_grid_slopes(const float* __restrict__ phi, int nx, int ny, int nz,
                                                      uint32_t* __restrict__ max3) {
-  const int64_t n = (int64_t)nx * ny * nz;
   float m[3] = {0.f, 0.f, 0.f};
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
-    const int i = (int)(q % nx);
-    const int j = (int)((q / nx) % ny);
-    const int k = (int)(q / ((int64_t)nx * ny));
-    const float v = phi[q];
-    if (i + 1 < nx) m[0] = fmaxf(m[0], fabsf(phi[q + 1] - v));
-    if (j + 1 < ny) m[1] = fmaxf(m[1], fabsf(phi[q + nx] - v));
-    if (k + 1 < nz) m[2] = fmaxf(m[2], fabsf(phi[q + (int64_t)nx * ny] - v));
+  const int64_t rows = (int64_t)ny * nz;
+  const int64_t plane = (int64_t)nx * ny;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {  // one x-row (j, k) per block iteration
+    const int j = (int)(row % ny), k = (int)(row / ny);
+    const float* r0 = phi + row * nx;
+    for (int i = threadIdx.x; i < nx; i += 256) {
+      const float v = r0[i];
+      if (i + 1 < nx) m[0] = fmaxf(m[0], fabsf(r0[i + 1] - v));
+      if (j + 1 < ny) m[1] = fmaxf(m[1], fabsf(r0[i + nx] - v));
+      if (k + 1 < nz) m[2] = fmaxf(m[2], fabsf(r0[i + plane] - v));
+    }
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -259,9 +261,8 @@ __global__ __launch_bounds__(256) void k_grid_slopes(const float* __restrict__ p
 }  // namespace
 
 hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream) {
-  const int64_t n = (int64_t)nx * ny * nz;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
+  int64_t blocks = (int64_t)ny * nz;
+  if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_grid_slopes, dim3((unsigned)blocks), dim3(256), 0, stream, phi, nx, ny, nz, max3);
   return hipGetLastError();
 }

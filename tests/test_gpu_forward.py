@@ -57,6 +57,8 @@ TUNINGS = [
     dict(block=128, tile_taxels=128, schedule=1, grid=7, order=1),
     dict(block=256, tile_taxels=256, schedule=2, grid=5, order=3),
     dict(block=128, schedule=2, grid=3, order=1),
+    dict(block=128, tile_taxels=128, schedule=0, order=4),
+    dict(block=256, tile_taxels=0, schedule=0, order=5),
 ]
 
 

@@ -20,7 +20,8 @@ KN = 1e4
 SCALE = np.array([5.0, 2.0, 2.0])
 TUNINGS = [dict(), dict(block=64, tile_taxels=64), dict(block=512, tile_taxels=512, order=2),
            dict(block=128, tile_taxels=128, schedule=2, grid=3, order=1),
-           dict(block=256, tile_taxels=256, schedule=1, grid=5, order=3)]
+           dict(block=256, tile_taxels=256, schedule=1, grid=5, order=3),
+           dict(block=128, tile_taxels=128, schedule=0, order=5)]
 
 
 def _say(msg):
