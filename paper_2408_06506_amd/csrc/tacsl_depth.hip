@@ -143,7 +143,10 @@ __device__ __forceinline__ float cell_first_root(const RayCell& rc, const float 
 
 __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t blk = (int64_t)blockIdx.x * 4 + wave;  // one 8 x 8 pixel block per wavefront
+  // workgroup b runs on XCD b % 8: XCD x takes the x-th contiguous share of
+  // the pad-major workgroup list, so each pad's rays share one L2
+  const int64_t wg = (int64_t)(blockIdx.x & 7u) * a.wg_per_xcd + (blockIdx.x >> 3);
+  const int64_t blk = wg * 4 + wave;  // one 8 x 8 pixel block per wavefront
   const int i = __builtin_amdgcn_readfirstlane((int)(blk / a.blocks_per_pad));
   if (i >= a.n_inst) return;
   const int b = (int)(blk - (int64_t)i * a.blocks_per_pad);
@@ -270,7 +273,10 @@ hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t
 hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream) {
   const int64_t blocks = (int64_t)a.n_inst * a.blocks_per_pad;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_depth_image, dim3((unsigned)((blocks + 3) / 4)), dim3(256), 0, stream, a);
+  const int64_t wgs = (blocks + 3) / 4;
+  DepthArgs b = a;
+  b.wg_per_xcd = (wgs + 7) / 8;
+  hipLaunchKernelGGL(k_depth_image, dim3((unsigned)(8 * b.wg_per_xcd)), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 

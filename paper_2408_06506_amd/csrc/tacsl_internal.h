@@ -176,6 +176,7 @@ struct DepthArgs {
   float cam_dist, gel;
   int32_t blocks_x;        // 8 x 8 blocks per image row of blocks
   int32_t blocks_per_pad;
+  int64_t wg_per_xcd;      // workgroups per XCD (set by the launcher)
   float* image;            // [n_inst][rows][cols]
   uint32_t* status;        // may be null
 };
