@@ -37,6 +37,9 @@
  *  - Pointers marked "host" are read during the call; pointers marked
  *    "device" must stay valid while the plan (or graph) uses them.  The
  *    library never frees caller memory.
+ *  - A plan's per-step buffers (prologue records, work-list order, queue,
+ *    partial sums) are shared by its calls: calls on one plan must be ordered
+ *    (one stream, or streams joined by events); overlapping calls race.
  *  - Every function returns an int status: TACSL_OK (0) or a negative
  *    tacsl_status code.  Host-side validation happens before any launch; on
  *    error nothing is launched and no output is touched.  Device-side
