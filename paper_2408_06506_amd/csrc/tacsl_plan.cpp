@@ -297,6 +297,34 @@ struct tacsl_graph_s {
 
 namespace {
 
+// Device buffers of one work list; installed into a plan only when complete.
+struct WorkBuffers {
+  Tile* tiles = nullptr;
+  int32_t* order = nullptr;
+  int64_t* inst_tile_begin = nullptr;
+  float* partial = nullptr;
+  double* bpartial = nullptr;
+  float* obs_partial = nullptr;
+  uint32_t* sp_hist = nullptr;
+  uint32_t* sp_cursor = nullptr;
+  int32_t* sp_bin = nullptr;
+  int32_t* sp_grp_tile = nullptr;
+  void release() {
+    dfree(tiles);
+    dfree(order);
+    dfree(inst_tile_begin);
+    dfree(partial);
+    dfree(bpartial);
+    dfree(obs_partial);
+    dfree(sp_hist);
+    dfree(sp_cursor);
+    dfree(sp_bin);
+    dfree(sp_grp_tile);
+  }
+};
+
+// Build and upload the work list of tuning t; the plan's previous work list
+// stays in place (and usable) if anything fails.
 int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
   std::vector<Tile> tiles;
   std::vector<int32_t> order;
@@ -304,31 +332,40 @@ int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
   const tacsl_scene_desc d = p->desc();
   int rc = make_worklist(d, t, kXcdCount, tiles, order, itb);
   if (rc != TACSL_OK) return rc;
-  p->free_worklist();
   const size_t n = tiles.size();
-  if (dalloc(&p->d_tiles, n) != hipSuccess || dalloc(&p->d_order, n) != hipSuccess ||
-      dalloc(&p->d_inst_tile_begin, itb.size()) != hipSuccess || dalloc(&p->d_partial, 6 * n) != hipSuccess ||
-      dalloc(&p->d_bpartial, (size_t)tacsl::kBwdAcc * n) != hipSuccess ||
-      (p->obs_n > 0 && dalloc(&p->d_obs_partial, (size_t)3 * p->obs_n * n) != hipSuccess)) {
-    p->free_worklist();
+  WorkBuffers w;
+  bool ok = dalloc(&w.tiles, n) == hipSuccess && dalloc(&w.order, n) == hipSuccess &&
+            dalloc(&w.inst_tile_begin, itb.size()) == hipSuccess && dalloc(&w.partial, 6 * n) == hipSuccess &&
+            dalloc(&w.bpartial, (size_t)tacsl::kBwdAcc * n) == hipSuccess &&
+            (p->obs_n == 0 || dalloc(&w.obs_partial, (size_t)3 * p->obs_n * n) == hipSuccess);
+  const size_t nb = (size_t)tacsl::kSpatialBins * std::max(p->n_sdf, 1);
+  if (ok && t.order == 5)
+    ok = dalloc(&w.sp_hist, nb) == hipSuccess && dalloc(&w.sp_cursor, nb) == hipSuccess &&
+         dalloc(&w.sp_bin, (size_t)p->n_inst) == hipSuccess &&
+         dalloc(&w.sp_grp_tile, (size_t)p->n_sdf + 1) == hipSuccess;
+  if (!ok) {
+    w.release();
     return TACSL_ERR_ALLOC;
   }
-  if (t.order == 5) {
-    const size_t nb = (size_t)tacsl::kSpatialBins * std::max(p->n_sdf, 1);
-    const size_t ni = (size_t)p->n_inst;
-    if (dalloc(&p->d_sp_hist, nb) != hipSuccess || dalloc(&p->d_sp_cursor, nb) != hipSuccess ||
-        dalloc(&p->d_sp_bin, ni) != hipSuccess || dalloc(&p->d_sp_grp_tile, (size_t)p->n_sdf + 1) != hipSuccess) {
-      p->free_worklist();
-      return TACSL_ERR_ALLOC;
-    }
-    if (hipMemset(p->d_sp_hist, 0, nb * sizeof(uint32_t)) != hipSuccess) return TACSL_ERR_HIP;
+  ok = (t.order != 5 || hipMemset(w.sp_hist, 0, nb * sizeof(uint32_t)) == hipSuccess) &&
+       (n == 0 || (hipMemcpy(w.tiles, tiles.data(), n * sizeof(Tile), hipMemcpyHostToDevice) == hipSuccess &&
+                   hipMemcpy(w.order, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess)) &&
+       hipMemcpy(w.inst_tile_begin, itb.data(), itb.size() * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    w.release();
+    return TACSL_ERR_HIP;
   }
-  if (n > 0 && (hipMemcpy(p->d_tiles, tiles.data(), n * sizeof(Tile), hipMemcpyHostToDevice) != hipSuccess ||
-                hipMemcpy(p->d_order, order.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess))
-    return TACSL_ERR_HIP;
-  if (hipMemcpy(p->d_inst_tile_begin, itb.data(), itb.size() * sizeof(int64_t), hipMemcpyHostToDevice) !=
-      hipSuccess)
-    return TACSL_ERR_HIP;
+  p->free_worklist();
+  p->d_tiles = w.tiles;
+  p->d_order = w.order;
+  p->d_inst_tile_begin = w.inst_tile_begin;
+  p->d_partial = w.partial;
+  p->d_bpartial = w.bpartial;
+  p->d_obs_partial = w.obs_partial;
+  p->d_sp_hist = w.sp_hist;
+  p->d_sp_cursor = w.sp_cursor;
+  p->d_sp_bin = w.sp_bin;
+  p->d_sp_grp_tile = w.sp_grp_tile;
   p->n_tiles = (int64_t)n;
   p->tun = t;
   return TACSL_OK;
