@@ -254,6 +254,24 @@ def run_backward(args, torch, api, wl):
     wb_t = torch.as_tensor(wb, device=plan.device)
     g = plan.backward(st, wa_t, wb_t)
     torch.cuda.synchronize()
+    # small launch-shape search for the adjoint (HIP events around each call)
+    best, best_ms = None, float("inf")
+    for tun in (dict(), dict(block=256, tile_taxels=0, schedule=0, order=3),
+                dict(block=256, tile_taxels=0, schedule=0, order=5), dict(block=256, tile_taxels=512, schedule=0, order=5),
+                dict(block=512, tile_taxels=0, schedule=0, order=5), dict(block=128, tile_taxels=0, schedule=0, order=5)):
+        plan.set_tuning(tun)
+        for _ in range(2):
+            plan.backward(st, wa_t, wb_t, g)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            plan.backward(st, wa_t, wb_t, g)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        if ms < best_ms:
+            best, best_ms = tun, ms
+    plan.set_tuning(best)
     for _ in range(3):
         plan.backward(st, wa_t, wb_t, g)
     steps = max(10, args.steps)
@@ -265,6 +283,7 @@ def run_backward(args, torch, api, wl):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms = plan.timer_read(steps)
+    plan_tuning = plan.tuning
     plan.close()
     V = sdf_footprint_nodes("differentiation_1024x2x40x50_128", sc)
     B = (24 * sc.n_taxels + 4 * V + 12 * int(sc.tmpl_offset[-1]) + (7 + 6) * 4 * sc.n_inst
@@ -273,7 +292,7 @@ def run_backward(args, torch, api, wl):
     log(f"backward: {wall * 1e3 / steps:.4f} ms/step, kernel {k_avg:.4f} ms")
     return {"workload": "differentiation: 1024 envs x 2 pads x 40x50 taxels, 5 objects at 128^3",
             "taxels": sc.n_taxels, "ms_per_step": wall * 1e3 / steps,
-            "taxel_evals_per_s": sc.n_taxels * steps / wall, "kernel": "k_force_bwd",
+            "taxel_evals_per_s": sc.n_taxels * steps / wall, "kernel": "k_force_bwd", "tuning": plan_tuning,
             "kernel_avg_ms": k_avg, "algorithmic_bytes_per_launch": B,
             "achieved_GBps": B / (k_avg * 1e-3) / 1e9, "frac_of_hbm_peak": B / (k_avg * 1e-3) / HBM_PEAK}
 

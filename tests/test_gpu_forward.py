@@ -207,3 +207,22 @@ def test_substep_graph_matches_eager(api):
                 assert torch.equal(outs[s][k], eager[s][k]), (rep, s, k)
     g.close()
     plan.close()
+
+
+def test_rejected_tuning_keeps_the_plan_usable(api):
+    """A tuning rejected by the library leaves the installed work list in place."""
+    from paper_2408_06506_amd import _abi
+    sc = wl.make_small(cfg_id=95, n_env=3)
+    plan = api.Plan(sc, dict(block=128, tile_taxels=128, order=5))
+    st = plan.state(sc.state())
+    ref = plan.forward(st)
+    torch.cuda.synchronize()
+    for bad in (dict(block=96), dict(order=6), dict(tile_taxels=10)):
+        with pytest.raises(_abi.TacslError):
+            plan.set_tuning(bad)
+    assert plan.tuning["order"] == 5 and plan.tuning["tile_taxels"] == 128
+    out = plan.forward(st)
+    torch.cuda.synchronize()
+    for k in ("depth", "normal", "fn", "ft", "wrench"):
+        assert torch.equal(out[k], ref[k]), k
+    plan.close()
