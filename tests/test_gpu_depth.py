@@ -162,3 +162,24 @@ def test_depth_errors_and_graph(api):
                                                  None, None), "depth")
     assert e.value.code == -7
     plan.close()
+
+
+def test_depth_single_negative_node(api):
+    """Oblique rays that enter and leave the object inside one cell: the
+    exact per-cell search must see the same bump as the oracle."""
+    from tests.test_oracle_depth import single_node_scene
+    sc, c = single_node_scene()
+    f = lambda v: float(np.float32(v))
+    vals = dict(rows=c["rows"], cols=c["cols"], ortho=c["ortho"], x0=f(c["x0"]), y0=f(c["y0"]), dx=f(c["dx"]),
+                dy=f(c["dy"]), cam_dist=f(c["cam_dist"]), gel=f(c["gel"]))
+    oc = oracle.Camera(vals["rows"], vals["cols"], vals["ortho"], vals["x0"], vals["y0"], vals["dx"], vals["dy"],
+                       vals["cam_dist"], vals["gel"])
+    _say("depth single negative node")
+    plan = api.Plan(sc)
+    plan.set_camera(**vals)
+    img = plan.depth_image(plan.state(sc.state()))
+    torch.cuda.synchronize()
+    ref, slope, pmin = oracle.depth_image(sc, oracle.state64(sc), oc)
+    frac = _check(sc, img.cpu().numpy(), ref, slope, pmin, oc, np.arange(sc.n_inst), "single node", max_mismatch=0.02)
+    assert frac > 0.03
+    plan.close()
