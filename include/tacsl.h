@@ -275,7 +275,9 @@ typedef struct {
   float cam_dist, gel;
 } tacsl_camera;
 
-/* Install (or with cam = NULL remove) the plan's tactile camera.  Host only;
+/* Install (or with cam = NULL remove) the plan's tactile camera.  The first
+ * call builds a copy of the object grids' node values laid out for the ray
+ * march (4 bytes per node; allocates and synchronizes, not inside capture).
  * TACSL_ERR_RANGE for invalid values. */
 int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam);
 

@@ -40,8 +40,12 @@ struct RayCell {
   float a[8];  // corner phi, index dx + 2 dy + 4 dz
 };
 
-__device__ __forceinline__ void ray_cell(const InstStatic& st, __amdgpu_buffer_rsrc_t rs, RayCell& rc, float ux,
-                                         float uy, float uz) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_f(const float* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes, kBufferFlags);
+}
+
+__device__ __forceinline__ void ray_cell(const InstStatic& st, const DepthGrid& g, __amdgpu_buffer_rsrc_t rs,
+                                         RayCell& rc, float ux, float uy, float uz) {
   // clamped on both sides: points on the box faces, and rounding just outside
   const int cx = min(max((int)floorf(ux), 0), st.nx - 2);
   const int cy = min(max((int)floorf(uy), 0), st.ny - 2);
@@ -50,19 +54,21 @@ __device__ __forceinline__ void ray_cell(const InstStatic& st, __amdgpu_buffer_r
   rc.cx = cx;
   rc.cy = cy;
   rc.cz = cz;
-  const uint32_t yz = __umul24((uint32_t)cy, st.stride_y) + (uint32_t)cz * 32u;
+  // x-quad columns: the two x-nodes by per-lane offsets, y by a scalar
+  // offset, z by an immediate offset
+  const uint32_t yz = __umul24((uint32_t)cy, g.stride_y) + (uint32_t)cz * 16u;
   const uint32_t x0 = (uint32_t)cx, x1 = x0 + 1u;
-  const uint32_t o0 = __umul24(x0 >> 1, st.stride_q) + (x0 & 1u) * 16u + yz;
-  const uint32_t o1 = __umul24(x1 >> 1, st.stride_q) + (x1 & 1u) * 16u + yz;
-  const uint32_t sy = st.stride_y;
+  const uint32_t o0 = __umul24(x0 >> 2, g.stride_q) + (x0 & 3u) * 4u + yz;
+  const uint32_t o1 = __umul24(x1 >> 2, g.stride_q) + (x1 & 3u) * 4u + yz;
+  const uint32_t sy = g.stride_y;
   rc.a[0] = load_phi(rs, o0, 0u);
   rc.a[1] = load_phi(rs, o1, 0u);
   rc.a[2] = load_phi(rs, o0, sy);
   rc.a[3] = load_phi(rs, o1, sy);
-  rc.a[4] = load_phi(rs, o0 + 32u, 0u);
-  rc.a[5] = load_phi(rs, o1 + 32u, 0u);
-  rc.a[6] = load_phi(rs, o0 + 32u, sy);
-  rc.a[7] = load_phi(rs, o1 + 32u, sy);
+  rc.a[4] = load_phi(rs, o0 + 16u, 0u);
+  rc.a[5] = load_phi(rs, o1 + 16u, 0u);
+  rc.a[6] = load_phi(rs, o0 + 16u, sy);
+  rc.a[7] = load_phi(rs, o1 + 16u, sy);
 }
 
 __device__ __forceinline__ float cell_tri(const RayCell& rc, float tx, float ty, float tz) {
@@ -143,19 +149,23 @@ __device__ __forceinline__ float cell_first_root(const RayCell& rc, const float 
 
 __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // workgroup b runs on XCD b % 8: XCD x takes the x-th contiguous share of
-  // the pad-major workgroup list, so each pad's rays share one L2
-  const int64_t wg = (int64_t)(blockIdx.x & 7u) * a.wg_per_xcd + (blockIdx.x >> 3);
-  const int64_t blk = wg * 4 + wave;  // one 8 x 8 pixel block per wavefront
-  const int i = __builtin_amdgcn_readfirstlane((int)(blk / a.blocks_per_pad));
-  if (i >= a.n_inst) return;
-  const int b = (int)(blk - (int64_t)i * a.blocks_per_pad);
+  // workgroup b runs on XCD b % 8; all workgroups of a pad stay on one XCD,
+  // which takes pad slots x, x + 8, x + 16, ... of the spatial order (each
+  // object's pads cut into one run per XCD): the pad's rays share one L2 and
+  // the next pad on that XCD is a spatial neighbour
+  const int64_t rank = blockIdx.x >> 3;  // this workgroup's rank on its XCD
+  const int64_t s = (rank / a.wg_per_pad) * 8 + (blockIdx.x & 7u);
+  if (s >= a.n_inst) return;
+  const int b = (int)(rank % a.wg_per_pad) * 4 + wave;  // one 8 x 8 pixel block per wavefront
+  if (b >= a.blocks_per_pad) return;
+  const int i = __builtin_amdgcn_readfirstlane(a.pad_order[s]);
   const int br = b / a.blocks_x, bc = b - br * a.blocks_x;
   const int r = br * 8 + (lane >> 3), c = bc * 8 + (lane & 7);
   if (r >= a.rows || c >= a.cols) return;
   const InstStatic st = a.stat[i];
   const InstXf x = a.xf[i];
-  const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
+  const DepthGrid g = a.grids[st.gid];
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc_f(g.phi, g.bytes);
   const float px = fmaf((float)c + 0.5f, a.dx, a.x0), py = fmaf((float)r + 0.5f, a.dy, a.y0);
   const float ex = a.ortho ? 0.f : px / a.cam_dist, ey = a.ortho ? 0.f : py / a.cam_dist;
   const float u0[3] = {fmaf(x.A[0], px, fmaf(x.A[1], py, x.b[0])), fmaf(x.A[3], px, fmaf(x.A[4], py, x.b[1])),
@@ -185,7 +195,7 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
     const float inv_ls = 1.f / (st.lip * sqrtf(fmaf(ex, ex, fmaf(ey, ey, 1.f))));
     float z = zlo;
     float u[3] = {fmaf(z, uz[0], u0[0]), fmaf(z, uz[1], u0[1]), fmaf(z, uz[2], u0[2])};
-    ray_cell(st, rs, rc, u[0], u[1], u[2]);
+    ray_cell(st, g, rs, rc, u[0], u[1], u[2]);
     float phi = cell_tri(rc, u[0] - (float)rc.cx, u[1] - (float)rc.cy, u[2] - (float)rc.cz);
     if (phi <= 0.f) {
       hit = true;
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
           u[0] = fmaf(z, uz[0], u0[0]);
           u[1] = fmaf(z, uz[1], u0[1]);
           u[2] = fmaf(z, uz[2], u0[2]);
-          ray_cell(st, rs, rc, u[0], u[1], u[2]);
+          ray_cell(st, g, rs, rc, u[0], u[1], u[2]);
           phi = cell_tri(rc, u[0] - (float)rc.cx, u[1] - (float)rc.cy, u[2] - (float)rc.cz);
           if (phi <= 0.f) {  // only by rounding at the step's end
             hit = true;
@@ -214,7 +224,7 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
         }
         // the rest of this cell, exactly; the cell is the one holding the open segment
         const float zm = 0.5f * (z + zend);
-        ray_cell(st, rs, rc, fmaf(zm, uz[0], u0[0]), fmaf(zm, uz[1], u0[1]), fmaf(zm, uz[2], u0[2]));
+        ray_cell(st, g, rs, rc, fmaf(zm, uz[0], u0[0]), fmaf(zm, uz[1], u0[1]), fmaf(zm, uz[2], u0[2]));
         const float p[3] = {fmaf(z, uz[0], u0[0]) - (float)rc.cx, fmaf(z, uz[1], u0[1]) - (float)rc.cy,
                             fmaf(z, uz[2], u0[2]) - (float)rc.cz};
         const float tau = cell_first_root(rc, p, uz, zend - z);
@@ -233,6 +243,22 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
   if (capped && a.status) atomicOr(a.status, TACSL_DEV_DEPTH_CAPPED);
   __builtin_nontemporal_store((hit ? zh : 0.f) + a.cam_dist,
                               a.image + (int64_t)i * a.rows * a.cols + (int64_t)r * a.cols + c);
+}
+
+// Node values of a prepared (phi, G) grid copied into x-quad columns.
+__global__ __launch_bounds__(256) void k_phi_quad(const float4* __restrict__ grid, int nx, int ny, int nz,
+                                                  float* __restrict__ out) {
+  const int64_t rows = (int64_t)ny * nz;
+  const uint32_t sy4 = 32u * (uint32_t)nz, sq4 = sy4 * (uint32_t)ny;      // (phi, G) layout strides
+  const int64_t qy = (int64_t)nz * 4, qq = qy * ny;                      // x-quad strides in floats
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int j = (int)(row / nz), k = (int)(row % nz);
+    for (int i = threadIdx.x; i < nx; i += 256) {
+      const uint32_t src = (uint32_t)(i >> 1) * sq4 + (uint32_t)j * sy4 + (uint32_t)k * 32u + (uint32_t)(i & 1) * 16u;
+      const float v = reinterpret_cast<const float*>(reinterpret_cast<const char*>(grid) + src)[0];
+      out[(int64_t)(i >> 2) * qq + (int64_t)j * qy + (int64_t)k * 4 + (i & 3)] = v;
+    }
+  }
 }
 
 // Largest node-to-node difference along each axis (|phi| units), for the
@@ -263,6 +289,13 @@ __global__ __launch_bounds__(256) void k_grid_slopes(const float* __restrict__ p
 
 }  // namespace
 
+hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* out, hipStream_t stream) {
+  int64_t blocks = (int64_t)ny * nz;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_phi_quad, dim3((unsigned)blocks), dim3(256), 0, stream, grid, nx, ny, nz, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream) {
   int64_t blocks = (int64_t)ny * nz;
   if (blocks > 8192) blocks = 8192;
@@ -271,12 +304,11 @@ hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t
 }
 
 hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream) {
-  const int64_t blocks = (int64_t)a.n_inst * a.blocks_per_pad;
-  if (blocks == 0) return hipSuccess;
-  const int64_t wgs = (blocks + 3) / 4;
+  if (a.n_inst == 0 || a.blocks_per_pad == 0) return hipSuccess;
   DepthArgs b = a;
-  b.wg_per_xcd = (wgs + 7) / 8;
-  hipLaunchKernelGGL(k_depth_image, dim3((unsigned)(8 * b.wg_per_xcd)), dim3(256), 0, stream, b);
+  b.wg_per_pad = (a.blocks_per_pad + 3) / 4;
+  const int64_t grid = 8 * (((int64_t)a.n_inst + 7) / 8) * b.wg_per_pad;
+  hipLaunchKernelGGL(k_depth_image, dim3((unsigned)grid), dim3(256), 0, stream, b);
   return hipGetLastError();
 }
 

@@ -81,6 +81,7 @@ struct PrologueArgs {
 constexpr int kSpatialBins = 512;
 struct SpatialArgs {
   int32_t n_inst, n_sdf, n_tiles;
+  int32_t interleave;              // 1: per-XCD interleave of each object's run; 0: plain spatial order
   uint32_t* hist;                  // [n_sdf * kSpatialBins] tiles per bin, left zeroed
   uint32_t* cursor;                // [n_sdf * kSpatialBins] next free tile position of each bin
   const int32_t* bin;              // [n_inst]
@@ -166,22 +167,37 @@ struct GradReduceArgs {
   int32_t n_env;
 };
 
+// Node values only, for the depth march ("x-quad columns"): node (i, j, k)
+// at byte (i >> 2) * stride_q + j * stride_y + 16 k + 4 (i & 3),
+// stride_y = 16 nz, stride_q = stride_y ny, so a 128-byte line holds 4 x-nodes
+// by 8 z-nodes at one y (four times the nodes of a line of (phi, G) records).
+inline int64_t phi_quad_bytes(int64_t nx, int64_t ny, int64_t nz) { return ((nx + 3) / 4) * ny * nz * 16; }
+struct DepthGrid {
+  const float* phi;
+  uint32_t bytes;
+  uint32_t stride_y, stride_q;
+  uint32_t pad_;
+};
+
 // Tactile depth image: per pad, pixels in 8 x 8 blocks (one wavefront each).
 struct DepthArgs {
   const InstStatic* stat;
   const InstXf* xf;
+  const DepthGrid* grids;  // [n_sdf] node values per object grid
+  const int32_t* pad_order;  // [n_inst] pads in the order their workgroups are dispatched
   int32_t n_inst;
   int32_t rows, cols, ortho;
   float x0, y0, dx, dy;  // pixel grid on the pad plane
   float cam_dist, gel;
   int32_t blocks_x;        // 8 x 8 blocks per image row of blocks
   int32_t blocks_per_pad;
-  int64_t wg_per_xcd;      // workgroups per XCD (set by the launcher)
+  int32_t wg_per_pad;      // workgroups per pad (set by the launcher)
   float* image;            // [n_inst][rows][cols]
   uint32_t* status;        // may be null
 };
 
 hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream);
+hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* out, hipStream_t stream);
 hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream);
 hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream);
 hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h,

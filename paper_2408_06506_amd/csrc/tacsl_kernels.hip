@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_sp_place(const SpatialArgs a) {
       seg = r + j2 / q;
       off = j2 - (seg - r) * q;
     }
-    const int slot = A + (off < q ? off * 8 + seg : 8 * q + seg);
+    const int slot = a.interleave ? A + (off < q ? off * 8 + seg : 8 * q + seg) : A + jr;
     if (slot >= 0 && slot < a.n_tiles) a.order[slot] = (int32_t)(t0 + k);  // always true when counts agree
   }
 }

@@ -192,12 +192,24 @@ struct tacsl_plan_s {
   std::vector<int64_t> inst_off;
   // scene copies needed to rebuild the work list
   std::vector<int32_t> inst_env, inst_tmpl, env_sdf;
+  std::vector<int32_t> sdf_dims;    // [n_sdf][3]
+  std::vector<int64_t> grid_base;   // [n_sdf + 1] float4 offsets of the prepared grids
   std::vector<int64_t> tmpl_offset;
   const float* tmpl_xyz = nullptr;  // plan-owned copy of the templates
   int64_t tmpl_T = 0;
   float* d_tmpl = nullptr;  // plan-owned copy of the templates
   // device buffers
   float4* grids = nullptr;
+  float* d_phi4 = nullptr;                 // node values in x-quad columns (depth image), built on demand
+  tacsl::DepthGrid* d_dgrid = nullptr;     // [n_sdf]
+  // spatial pad order of the depth image (one unit per pad)
+  uint32_t* d_dsp_hist = nullptr;
+  uint32_t* d_dsp_cursor = nullptr;
+  int32_t* d_dsp_bin = nullptr;
+  int32_t* d_dsp_grp = nullptr;
+  int64_t* d_dsp_units = nullptr;          // [n_inst + 1] = 0, 1, ..., n_inst
+  int32_t* d_dsp_order = nullptr;          // [n_inst]
+  int64_t phi4_bytes = 0;
   int64_t grids_bytes = 0;
   InstStatic* d_stat = nullptr;
   InstXf* d_xf = nullptr;
@@ -285,6 +297,14 @@ struct tacsl_plan_s {
     dfree(d_queue);
     dfree(d_env_inst_begin);
     dfree(d_env_inst);
+    dfree(d_phi4);
+    dfree(d_dgrid);
+    dfree(d_dsp_hist);
+    dfree(d_dsp_cursor);
+    dfree(d_dsp_bin);
+    dfree(d_dsp_grp);
+    dfree(d_dsp_units);
+    dfree(d_dsp_order);
     free_observation();
   }
 };
@@ -379,6 +399,7 @@ int enqueue_spatial(tacsl_plan p, hipStream_t stream) {
   sa.n_inst = p->n_inst;
   sa.n_sdf = p->n_sdf;
   sa.n_tiles = (int32_t)p->n_tiles;
+  sa.interleave = 1;
   sa.hist = p->d_sp_hist;
   sa.cursor = p->d_sp_cursor;
   sa.bin = p->d_sp_bin;
@@ -579,6 +600,8 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     gbase[g + 1] = gbase[g] + tacsl::prepared_grid_bytes(d.sdf_dims[3 * g], d.sdf_dims[3 * g + 1],
                                                          d.sdf_dims[3 * g + 2]) / (int64_t)sizeof(float4);
   p->grids_bytes = gbase[d.n_sdf] * (int64_t)sizeof(float4);
+  p->grid_base = gbase;
+  p->sdf_dims.assign(d.sdf_dims, d.sdf_dims + 3 * d.n_sdf);
   if (dalloc(&p->grids, (size_t)gbase[d.n_sdf]) != hipSuccess) return fail(TACSL_ERR_ALLOC);
   uint32_t* d_bad = nullptr;
   if (dalloc(&d_bad, 1) != hipSuccess) return fail(TACSL_ERR_ALLOC);
@@ -804,6 +827,67 @@ int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam) {
   for (float v : f)
     if (!std::isfinite(v)) return TACSL_ERR_RANGE;
   if (!(c.dx > 0.f) || !(c.dy > 0.f) || !(c.gel > 0.f) || !(c.cam_dist >= c.gel)) return TACSL_ERR_RANGE;
+  if (!plan->d_phi4 && plan->n_sdf > 0) {
+    // node values in x-quad columns for the ray march (built once)
+    std::vector<tacsl::DepthGrid> dg((size_t)plan->n_sdf);
+    std::vector<int64_t> base((size_t)plan->n_sdf + 1, 0);
+    for (int g = 0; g < plan->n_sdf; ++g)
+      base[g + 1] = base[g] + tacsl::phi_quad_bytes(plan->sdf_dims[3 * g], plan->sdf_dims[3 * g + 1],
+                                                    plan->sdf_dims[3 * g + 2]) / (int64_t)sizeof(float);
+    float* d_phi4 = nullptr;
+    tacsl::DepthGrid* d_dg = nullptr;
+    if (hipDeviceSynchronize() != hipSuccess) return TACSL_ERR_HIP;
+    if (dalloc(&d_phi4, (size_t)base[plan->n_sdf]) != hipSuccess || dalloc(&d_dg, dg.size()) != hipSuccess) {
+      dfree(d_phi4);
+      dfree(d_dg);
+      return TACSL_ERR_ALLOC;
+    }
+    bool ok = hipMemset(d_phi4, 0, (size_t)base[plan->n_sdf] * sizeof(float)) == hipSuccess;
+    for (int g = 0; ok && g < plan->n_sdf; ++g) {
+      const int nx = plan->sdf_dims[3 * g], ny = plan->sdf_dims[3 * g + 1], nz = plan->sdf_dims[3 * g + 2];
+      dg[g].phi = d_phi4 + base[g];
+      dg[g].bytes = (uint32_t)((base[g + 1] - base[g]) * (int64_t)sizeof(float));
+      dg[g].stride_y = 16u * (uint32_t)nz;
+      dg[g].stride_q = dg[g].stride_y * (uint32_t)ny;
+      dg[g].pad_ = 0;
+      ok = tacsl::launch_phi_quad(plan->grids + plan->grid_base[g], nx, ny, nz, d_phi4 + base[g], nullptr) ==
+           hipSuccess;
+    }
+    ok = ok && hipMemcpy(d_dg, dg.data(), dg.size() * sizeof(tacsl::DepthGrid), hipMemcpyHostToDevice) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+      dfree(d_phi4);
+      dfree(d_dg);
+      return TACSL_ERR_HIP;
+    }
+    plan->d_phi4 = d_phi4;
+    plan->d_dgrid = d_dg;
+    plan->phi4_bytes = base[plan->n_sdf] * (int64_t)sizeof(float);
+  }
+  if (!plan->d_dsp_order && plan->n_inst > 0) {
+    const size_t nb = (size_t)tacsl::kSpatialBins * plan->n_sdf, ni = (size_t)plan->n_inst;
+    std::vector<int64_t> units(ni + 1);
+    std::iota(units.begin(), units.end(), int64_t(0));
+    std::vector<int32_t> ident(ni);
+    std::iota(ident.begin(), ident.end(), 0);
+    bool ok = dalloc(&plan->d_dsp_hist, nb) == hipSuccess && dalloc(&plan->d_dsp_cursor, nb) == hipSuccess &&
+              dalloc(&plan->d_dsp_bin, ni) == hipSuccess && dalloc(&plan->d_dsp_grp, (size_t)plan->n_sdf + 1) == hipSuccess &&
+              dalloc(&plan->d_dsp_units, ni + 1) == hipSuccess && dalloc(&plan->d_dsp_order, ni) == hipSuccess;
+    ok = ok && hipMemset(plan->d_dsp_hist, 0, nb * sizeof(uint32_t)) == hipSuccess &&
+         hipMemcpy(plan->d_dsp_units, units.data(), units.size() * sizeof(int64_t), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(plan->d_dsp_order, ident.data(), ident.size() * sizeof(int32_t), hipMemcpyHostToDevice) ==
+             hipSuccess;
+    if (!ok) {
+      dfree(plan->d_dsp_hist);
+      dfree(plan->d_dsp_cursor);
+      dfree(plan->d_dsp_bin);
+      dfree(plan->d_dsp_grp);
+      dfree(plan->d_dsp_units);
+      dfree(plan->d_dsp_order);
+      return TACSL_ERR_ALLOC;
+    }
+  }
   plan->cam = c;
   plan->has_cam = true;
   return TACSL_OK;
@@ -830,11 +914,30 @@ int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, u
   pa.status = status;
   pa.queue = plan->d_queue;
   pa.hc = plan->hc;
+  pa.sp_hist = plan->d_dsp_hist;
+  pa.sp_bin = plan->d_dsp_bin;
+  pa.sp_inst_tile_begin = plan->d_dsp_units;
   if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+  // pads in spatial order, object by object, each object's run cut into
+  // one share per XCD (pad slot s is drawn by XCD s % 8)
+  tacsl::SpatialArgs sa{};
+  sa.n_inst = plan->n_inst;
+  sa.n_sdf = plan->n_sdf;
+  sa.n_tiles = plan->n_inst;
+  sa.interleave = 1;
+  sa.hist = plan->d_dsp_hist;
+  sa.cursor = plan->d_dsp_cursor;
+  sa.bin = plan->d_dsp_bin;
+  sa.grp_tile_begin = plan->d_dsp_grp;
+  sa.inst_tile_begin = plan->d_dsp_units;
+  sa.order = plan->d_dsp_order;
+  if (tacsl::launch_spatial_order(sa, stream) != hipSuccess) return TACSL_ERR_HIP;
   const tacsl_camera& c = plan->cam;
   tacsl::DepthArgs da{};
   da.stat = plan->d_stat;
   da.xf = plan->d_xf;
+  da.grids = plan->d_dgrid;
+  da.pad_order = plan->d_dsp_order;
   da.n_inst = plan->n_inst;
   da.rows = c.rows;
   da.cols = c.cols;
