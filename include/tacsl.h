@@ -175,7 +175,7 @@ typedef struct {
   int32_t cu_count;          /* compute units of the plan's device */
   int32_t xcd_count;         /* XCDs assumed by the XCD-aware order */
   int64_t prepared_bytes;    /* device bytes of the prepared SDF pool */
-  int64_t workspace_bytes;   /* device bytes of the plan's other buffers */
+  int64_t workspace_bytes;   /* device bytes of the plan's other buffers, as allocated at the call */
   tacsl_tuning tuning;       /* resolved tuning (defaults filled in) */
 } tacsl_plan_info;
 

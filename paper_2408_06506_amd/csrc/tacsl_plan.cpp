@@ -239,7 +239,18 @@ struct tacsl_plan_s {
   int32_t* d_sp_bin = nullptr;
   int32_t* d_sp_grp_tile = nullptr;
   int64_t n_tiles = 0;
-  int64_t ws_bytes = 0;
+  // device bytes of everything but the prepared SDF pool (what is allocated now)
+  int64_t workspace_bytes() const {
+    const int64_t ni = n_inst, nt = n_tiles, ns = n_sdf;
+    int64_t b = ni * (int64_t)(sizeof(InstStatic) + sizeof(InstXf)) + 3 * tmpl_T * (int64_t)sizeof(float) +
+                nt * (int64_t)(sizeof(Tile) + sizeof(int32_t) + 6 * sizeof(float) + tacsl::kBwdAcc * sizeof(double)) +
+                (ni + 1) * (int64_t)sizeof(int64_t) + (n_env + 1 + ni) * 4 + 4;
+    if (obs_n > 0) b += tmpl_T * 4 + ns * obs_n * 4 + ni * 4 + nt * 3 * obs_n * 4;
+    if (d_sp_hist) b += 2 * tacsl::kSpatialBins * ns * 4 + ni * 4 + (ns + 1) * 4;
+    if (d_phi4) b += phi4_bytes + ns * (int64_t)sizeof(tacsl::DepthGrid);
+    if (d_dsp_hist) b += 2 * tacsl::kSpatialBins * ns * 4 + ni * 4 + (ns + 1) * 4 + (ni + 1) * 8 + ni * 4;
+    return b;
+  }
   int live_graphs = 0;
   // kernel timer (instrumentation)
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -693,11 +704,6 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     return fail(TACSL_ERR_HIP);
   rc = install_worklist(p, t);
   if (rc != TACSL_OK) return fail(rc);
-  p->ws_bytes = (int64_t)(st.size() * sizeof(InstStatic) + (size_t)d.n_inst * sizeof(InstXf) +
-                          (size_t)p->tmpl_T * 16 +
-                          (size_t)p->n_tiles * (sizeof(Tile) + sizeof(int32_t) + 6 * sizeof(float) +
-                                                tacsl::kBwdAcc * sizeof(double)) +
-                          ((size_t)d.n_inst + 1) * sizeof(int64_t) + eib.size() * 4 + ei.size() * 4 + 4);
   if (hipDeviceSynchronize() != hipSuccess) return fail(TACSL_ERR_HIP);
   *out = p;
   return TACSL_OK;
@@ -722,7 +728,7 @@ int tacsl_plan_get_info(tacsl_plan plan, tacsl_plan_info* info) {
   info->cu_count = plan->cu_count;
   info->xcd_count = kXcdCount;
   info->prepared_bytes = plan->grids_bytes;
-  info->workspace_bytes = plan->ws_bytes;
+  info->workspace_bytes = plan->workspace_bytes();
   info->tuning = plan->tun;
   return TACSL_OK;
 }
