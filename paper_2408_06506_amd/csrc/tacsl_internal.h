@@ -14,8 +14,28 @@ namespace tacsl {
 // so one 128-byte line holds 2 x-nodes by 4 z-nodes at one y: the eight
 // corners of a cell are reached from 2 per-lane offsets (x and x+1), with the
 // y step as a scalar offset and the z step as an immediate offset.
+inline int64_t grid_record_bytes(int64_t nx, int64_t ny, int64_t nz) { return ((nx + 1) / 2) * ny * nz * 32; }
+
+// Clear-block mask, stored after the records of each prepared grid: one bit
+// per block of 2 x 2 x 2 cells (block b spans nodes 2b .. 2b + 2 per axis,
+// clamped to the grid), set when every node value of the block is > 0.  A
+// trilinear value inside such a block is then >= 0 in FP32 as well (each
+// lerp of non-negative values rounds to a non-negative value), so a taxel
+// whose cell lies in a set block is out of contact without its corners.  A
+// 32-bit word holds 4 x 4 x 2 blocks (bit (bx & 3) + 4 (by & 3) + 16 (bz & 1));
+// word (wx, wy, wz) sits at byte 4 ((wx W_y + wy) W_z + wz) of the mask.
+struct MaskDims {
+  int64_t wx, wy, wz;
+};
+inline MaskDims mask_dims(int64_t nx, int64_t ny, int64_t nz) {
+  return {(nx / 2 + 3) / 4, (ny / 2 + 3) / 4, (nz / 2 + 1) / 2};
+}
+inline int64_t grid_mask_bytes(int64_t nx, int64_t ny, int64_t nz) {
+  const MaskDims m = mask_dims(nx, ny, nz);
+  return (4 * m.wx * m.wy * m.wz + 15) / 16 * 16;
+}
 inline int64_t prepared_grid_bytes(int64_t nx, int64_t ny, int64_t nz) {
-  return ((nx + 1) / 2) * ny * nz * 32;
+  return grid_record_bytes(nx, ny, nz) + grid_mask_bytes(nx, ny, nz);
 }
 
 // Static per-pad record, built at plan creation (device, read-only).
@@ -32,6 +52,9 @@ struct InstStatic {
   float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
   float lip;            // bound on |grad phi| of the trilinear field (edge slopes combined)
   int32_t gid;          // object grid index
+  uint32_t mask_off;    // byte offset of the clear-block mask within the prepared grid
+  uint32_t mask_sx;     // mask bytes between consecutive x-words (4 W_y W_z)
+  uint32_t mask_sy;     // mask bytes between consecutive y-words (4 W_z)
 };
 
 // Per-step per-pad record written by the prologue (FP64 math, FP32 store).
@@ -200,6 +223,7 @@ hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream);
 hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* out, hipStream_t stream);
 hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream);
 hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream);
+hipError_t launch_clear_mask(const float* phi, uint32_t* mask, int nx, int ny, int nz, hipStream_t stream);
 hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h,
                                uint32_t* bad_count, hipStream_t stream);
 hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream);

@@ -36,6 +36,30 @@
 namespace tacsl {
 namespace {
 
+// Clear-block mask (layout in tacsl_internal.h): one thread per 32-bit word.
+__global__ __launch_bounds__(256) void k_clear_mask(const float* __restrict__ phi, uint32_t* __restrict__ mask,
+                                                    int nx, int ny, int nz, int wx, int wy, int wz) {
+  const int64_t n = (int64_t)wx * wy * wz;
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n) return;
+  const int iz = (int)(w % wz), iy = (int)((w / wz) % wy), ix = (int)(w / ((int64_t)wz * wy));
+  uint32_t bits = 0u;
+  for (int b = 0; b < 32; ++b) {
+    const int bx = 4 * ix + (b & 3), by = 4 * iy + ((b >> 2) & 3), bz = 2 * iz + (b >> 4);
+    if (2 * bx > nx - 2 || 2 * by > ny - 2 || 2 * bz > nz - 2) continue;  // no cell starts in this block
+    bool clear = true;
+    for (int k = 2 * bz; clear && k <= min(2 * bz + 2, nz - 1); ++k)
+      for (int j = 2 * by; clear && j <= min(2 * by + 2, ny - 1); ++j)
+        for (int i = 2 * bx; i <= min(2 * bx + 2, nx - 1); ++i)
+          if (!(phi[((int64_t)k * ny + j) * nx + i] > 0.f)) {
+            clear = false;
+            break;
+          }
+    if (clear) bits |= 1u << b;
+  }
+  mask[w] = bits;
+}
+
 // ---------------------------------------------------------------------------
 // SDF preparation: (phi, G) per node, G = nodal finite differences (central
 // inside, one-sided on the faces), stored in the x-pair column layout.
@@ -299,6 +323,13 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   f.tx = f.ux - (float)cx;
   f.ty = f.uy - (float)cy;
   f.tz = f.uz - (float)cz;
+  {
+    // cells in a clear block are out of contact: skip their eight gathers
+    const uint32_t bx = (uint32_t)cx >> 1, by = (uint32_t)cy >> 1, bz = (uint32_t)cz >> 1;
+    const uint32_t mo = st.mask_off + __umul24(bx >> 2, st.mask_sx) + __umul24(by >> 2, st.mask_sy) + (bz >> 1) * 4u;
+    const uint32_t word = __builtin_amdgcn_raw_buffer_load_b32(rs, mo, 0u, 0);
+    if ((word >> ((bx & 3u) | ((by & 3u) << 2) | ((bz & 1u) << 4))) & 1u) return;
+  }
   // per-lane offsets of the two x-nodes; y steps are scalar, z steps
   // immediate.  Plan creation keeps stride_q = 32 ny nz below 2^24 (and so
   // stride_y and the cell indices), so the products fit the full-rate 24-bit
@@ -787,6 +818,14 @@ hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, in
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_prepare_grid, dim3((unsigned)blocks), dim3(256), 0, stream, phi, out, nx, ny, nz, h, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_mask(const float* phi, uint32_t* mask, int nx, int ny, int nz, hipStream_t stream) {
+  const MaskDims m = mask_dims(nx, ny, nz);
+  const int64_t n = m.wx * m.wy * m.wz;
+  hipLaunchKernelGGL(k_clear_mask, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, phi, mask, nx, ny, nz,
+                     (int)m.wx, (int)m.wy, (int)m.wz);
   return hipGetLastError();
 }
 

@@ -605,7 +605,8 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   for (int i = 0; i < d.n_inst; ++i) p->inst_off[i + 1] = p->inst_off[i] + tmpl_count(d, i);
   p->T = p->inst_off[d.n_inst];
 
-  // prepared SDF pool: (phi, G) float4 records in x-pair columns
+  // prepared SDF pool: per grid, (phi, G) float4 records in x-pair columns and
+  // the clear-block mask after them
   std::vector<int64_t> gbase((size_t)d.n_sdf + 1, 0);
   for (int g = 0; g < d.n_sdf; ++g)
     gbase[g + 1] = gbase[g] + tacsl::prepared_grid_bytes(d.sdf_dims[3 * g], d.sdf_dims[3 * g + 1],
@@ -621,9 +622,12 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     return fail(TACSL_ERR_HIP);
   }
   for (int g = 0; g < d.n_sdf; ++g) {
-    if (tacsl::launch_prepare_grid(d.sdf_data + d.sdf_offset[g], p->grids + gbase[g], d.sdf_dims[3 * g],
-                                   d.sdf_dims[3 * g + 1], d.sdf_dims[3 * g + 2], d.sdf_spacing[g], d_bad,
-                                   nullptr) != hipSuccess) {
+    const int nx = d.sdf_dims[3 * g], ny = d.sdf_dims[3 * g + 1], nz = d.sdf_dims[3 * g + 2];
+    uint32_t* mask = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(p->grids + gbase[g]) +
+                                                 tacsl::grid_record_bytes(nx, ny, nz));
+    if (tacsl::launch_prepare_grid(d.sdf_data + d.sdf_offset[g], p->grids + gbase[g], nx, ny, nz, d.sdf_spacing[g],
+                                   d_bad, nullptr) != hipSuccess ||
+        tacsl::launch_clear_mask(d.sdf_data + d.sdf_offset[g], mask, nx, ny, nz, nullptr) != hipSuccess) {
       dfree(d_bad);
       return fail(TACSL_ERR_HIP);
     }
@@ -681,6 +685,10 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     s.h = d.sdf_spacing[g];
     s.lip = lip[g];
     s.gid = g;
+    const tacsl::MaskDims md = tacsl::mask_dims(s.nx, s.ny, s.nz);
+    s.mask_off = (uint32_t)tacsl::grid_record_bytes(s.nx, s.ny, s.nz);
+    s.mask_sx = (uint32_t)(4 * md.wy * md.wz);
+    s.mask_sy = (uint32_t)(4 * md.wz);
   }
   // environments -> pads (ascending)
   std::vector<int32_t> eib((size_t)d.n_env + 1, 0), ei((size_t)d.n_inst);
