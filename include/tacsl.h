@@ -290,7 +290,7 @@ int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam);
  * sphere-tracing steps (with a per-grid bound on |grad phi|) where they
  * leave the current cell, else an exact search of the rest of the cell (the
  * field is a cubic along the ray, split at the roots of its derivative, the
- * first sign change bisected).  A ray that needs more than 4096 iterations
+ * first sign change refined by safeguarded Newton steps).  A ray that needs more than 4096 iterations
  * (more grid planes than that inside the gel) reads the gel surface and sets
  * TACSL_DEV_DEPTH_CAPPED in *status (optional device word).  TACSL_ERR_STATE
  * without a camera.  Asynchronous on

@@ -24,8 +24,9 @@ namespace {
 // phi / (lip s) cannot pass the surface, and it is taken whenever it reaches
 // past the current cell.  Otherwise the rest of the cell is searched exactly:
 // along the ray the trilinear field is a cubic in z, monotone between the
-// roots of its derivative, so its sign at those points and at the cell exit
-// brackets the first root, which is bisected with the direct trilinear form.
+// roots of its derivative, so its sign (direct trilinear form) at those points
+// and at the cell exit brackets the first root, which safeguarded Newton steps
+// on the cubic then refine.
 // Every iteration moves past at least one grid plane, so the work per ray is
 // bounded by the planes it crosses.
 // ---------------------------------------------------------------------------
@@ -75,18 +76,19 @@ __device__ __forceinline__ float cell_tri(const RayCell& rc, float tx, float ty,
   return tri(rc.a[0], rc.a[1], rc.a[2], rc.a[3], rc.a[4], rc.a[5], rc.a[6], rc.a[7], tx, ty, tz);
 }
 
-// Height of the next grid plane of one axis strictly above z.
-__device__ __forceinline__ float next_plane(float u0, float uz, float z) {
+// Height of the next grid plane of one axis strictly above z (iuz = 1 / uz).
+// A crossing height that rounds onto z moves on to the following plane.
+__device__ __forceinline__ float next_plane(float u0, float uz, float iuz, float z) {
   if (uz == 0.f) return INFINITY;
   const float dir = uz > 0.f ? 1.f : -1.f;
   const float ua = fmaf(z, uz, u0);
   float plane = uz > 0.f ? floorf(ua) + 1.f : ceilf(ua) - 1.f;
-  float zc = (plane - u0) / uz;
+  float zc = (plane - u0) * iuz;
   for (int k = 0; k < 3 && !(zc > z); ++k) {
     plane += dir;
-    zc = (plane - u0) / uz;
+    zc = (plane - u0) * iuz;
   }
-  return zc > z ? zc : z + fabsf(1.f / uz);
+  return zc > z ? zc : z + fabsf(iuz);
 }
 
 // First root of the field on the ray segment [z, z + len] inside cell rc,
@@ -131,16 +133,28 @@ __device__ __forceinline__ float cell_first_root(const RayCell& rc, const float 
     const float tj = pts[j];
     if (!(tj > lo && tj <= len)) continue;  // outside the segment (or NaN)
     if (cell_tri(rc, fmaf(tj, q[0], p[0]), fmaf(tj, q[1], p[1]), fmaf(tj, q[2], p[2])) <= 0.f) {
-      float hi = tj;  // phi(lo) > 0 >= phi(hi), monotone in between
-      for (int k = 0; k < 30; ++k) {
-        const float mid = 0.5f * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        if (cell_tri(rc, fmaf(mid, q[0], p[0]), fmaf(mid, q[1], p[1]), fmaf(mid, q[2], p[2])) <= 0.f)
-          hi = mid;
+      // phi(lo) > 0 >= phi(hi) and phi is monotone in between: Newton steps
+      // on the cubic, kept inside the shrinking bracket (a step that leaves
+      // it is replaced by the bracket's midpoint), until a step is below
+      // 1e-6 of the segment
+      float hi = tj;
+      const float c0 = cell_tri(rc, p[0], p[1], p[2]);
+      float t = 0.5f * (lo + hi);
+      for (int k = 0; k < 8; ++k) {
+        const float f = fmaf(t, fmaf(t, fmaf(t, c3, c2), c1), c0);
+        if (f == 0.f) break;
+        if (f > 0.f)
+          lo = t;
         else
-          lo = mid;
+          hi = t;
+        const float d = fmaf(t, fmaf(t, 3.f * c3, 2.f * c2), c1);
+        float tn = t - f / d;
+        if (!(tn >= lo && tn <= hi)) tn = 0.5f * (lo + hi);  // also catches d == 0 (inf / NaN)
+        const bool done = fabsf(tn - t) <= 1e-6f * len;
+        t = tn;
+        if (done) break;
       }
-      return hi;
+      return t;
     }
     lo = tj;
   }
@@ -193,6 +207,7 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
     rc.cy = -1;
     rc.cz = -1;
     const float inv_ls = 1.f / (st.lip * sqrtf(fmaf(ex, ex, fmaf(ey, ey, 1.f))));
+    const float iuz[3] = {1.f / uz[0], 1.f / uz[1], 1.f / uz[2]};
     float z = zlo;
     float u[3] = {fmaf(z, uz[0], u0[0]), fmaf(z, uz[1], u0[1]), fmaf(z, uz[2], u0[2])};
     ray_cell(st, g, rs, rc, u[0], u[1], u[2]);
@@ -203,8 +218,8 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
     } else {
       int it = 0;
       for (; it < kDepthMaxIter; ++it) {
-        const float ze = fminf(fminf(next_plane(u0[0], uz[0], z), next_plane(u0[1], uz[1], z)),
-                               next_plane(u0[2], uz[2], z));
+        const float ze = fminf(fminf(next_plane(u0[0], uz[0], iuz[0], z), next_plane(u0[1], uz[1], iuz[1], z)),
+                               next_plane(u0[2], uz[2], iuz[2], z));
         const float zend = fminf(ze, zhi);
         const float zs = z + phi * inv_ls;
         if (zs >= zend) {  // a safe step that leaves the cell
