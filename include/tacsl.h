@@ -287,8 +287,8 @@ int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam);
  * SDF is <= 0, or cam_dist (the undeformed gel surface) when the ray meets no
  * object inside the gel and the object's grid box.  An object reaching
  * below the gel reads cam_dist - gel.  The ray advances cell by cell:
- * sphere-tracing steps (with a per-grid bound on |grad phi|) where they
- * leave the current cell, else an exact search of the rest of the cell (the
+ * sphere-tracing steps (with bounds on the field's slopes near the current
+ * block of 8 x 8 x 8 cells) where they leave the current cell, else an exact search of the rest of the cell (the
  * field is a cubic along the ray, split at the roots of its derivative, the
  * first sign change refined by safeguarded Newton steps).  A ray that needs more than 4096 iterations
  * (more grid planes than that inside the gel) reads the gel surface and sets

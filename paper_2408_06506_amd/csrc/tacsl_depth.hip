@@ -1,5 +1,5 @@
 // Tactile depth image kernels of libtacsl for gfx950 (MI355X), and the
-// per-grid Lipschitz bound the ray march relies on.
+// local slope bounds the ray march relies on.
 #include <hip/hip_runtime.h>
 
 #include "tacsl.h"
@@ -20,9 +20,10 @@ namespace {
 // box) where the trilinear phi <= 0, or cam_dist (the gel surface).
 //
 // The ray advances cell by cell.  Far from the surface it takes sphere-tracing
-// steps: with |grad phi| <= lip (per grid) and s = |dX/dz|, a step of
-// phi / (lip s) cannot pass the surface, and it is taken whenever it reaches
-// past the current cell.  Otherwise the rest of the cell is searched exactly:
+// steps: near the current block, |d phi / dz| <= sum_k m_k |duk/dz| with m_k
+// the block's slope bounds (per grid step, see DepthGrid), so a step of phi
+// over that sum, kept within 7 cells so that it stays near the block, cannot
+// pass the surface; it is taken whenever it reaches past the current cell.  Otherwise the rest of the cell is searched exactly:
 // along the ray the trilinear field is a cubic in z, monotone between the
 // roots of its derivative, so its sign (direct trilinear form) at those points
 // and at the cell exit brackets the first root, which safeguarded Newton steps
@@ -136,11 +137,13 @@ __device__ __forceinline__ float cell_first_root(const RayCell& rc, const float 
       // phi(lo) > 0 >= phi(hi) and phi is monotone in between: Newton steps
       // on the cubic, kept inside the shrinking bracket (a step that leaves
       // it is replaced by the bracket's midpoint), until a step is below
-      // 1e-6 of the segment
+      // 1e-6 of the segment.  A root close to one end of a long bracket can
+      // send several Newton steps out of it before they converge, so the cap
+      // is set by the bisections alone: 40 halvings reach 1e-12 of the segment.
       float hi = tj;
       const float c0 = cell_tri(rc, p[0], p[1], p[2]);
       float t = 0.5f * (lo + hi);
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < 40; ++k) {
         const float f = fmaf(t, fmaf(t, fmaf(t, c3, c2), c1), c0);
         if (f == 0.f) break;
         if (f > 0.f)
@@ -206,7 +209,8 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
     rc.cx = -1;
     rc.cy = -1;
     rc.cz = -1;
-    const float inv_ls = 1.f / (st.lip * sqrtf(fmaf(ex, ex, fmaf(ey, ey, 1.f))));
+    const float au[3] = {fabsf(uz[0]), fabsf(uz[1]), fabsf(uz[2])};
+    const float zcap = 7.f / fmaxf(au[0], fmaxf(au[1], au[2]));  // at most 7 cells along any axis
     const float iuz[3] = {1.f / uz[0], 1.f / uz[1], 1.f / uz[2]};
     float z = zlo;
     float u[3] = {fmaf(z, uz[0], u0[0]), fmaf(z, uz[1], u0[1]), fmaf(z, uz[2], u0[2])};
@@ -221,7 +225,10 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
         const float ze = fminf(fminf(next_plane(u0[0], uz[0], iuz[0], z), next_plane(u0[1], uz[1], iuz[1], z)),
                                next_plane(u0[2], uz[2], iuz[2], z));
         const float zend = fminf(ze, zhi);
-        const float zs = z + phi * inv_ls;
+        // the block of the current cell: the point is in it or on its boundary
+        const float4 m = g.slope[((rc.cx >> 3) * g.sby + (rc.cy >> 3)) * g.sbz + (rc.cz >> 3)];
+        const float bnd = fmaf(m.x, au[0], fmaf(m.y, au[1], m.z * au[2])) * 1.00002f;  // rounding margin
+        const float zs = z + fminf(phi / bnd, zcap);  // phi > 0 here; bnd == 0 gives the cap
         if (zs >= zend) {  // a safe step that leaves the cell
           if (zs >= zhi) break;
           z = zs;
@@ -276,30 +283,50 @@ __global__ __launch_bounds__(256) void k_phi_quad(const float4* __restrict__ gri
   }
 }
 
-// Largest node-to-node difference along each axis (|phi| units), for the
-// Lipschitz bound of the trilinear field.  max3 holds float bits (>= 0).
-__global__ __launch_bounds__(256) void k_grid_slopes(const float* __restrict__ phi, int nx, int ny, int nz,
-                                                     uint32_t* __restrict__ max3) {
-  float m[3] = {0.f, 0.f, 0.f};
-  const int64_t rows = (int64_t)ny * nz;
-  const int64_t plane = (int64_t)nx * ny;
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {  // one x-row (j, k) per block iteration
-    const int j = (int)(row % ny), k = (int)(row / ny);
-    const float* r0 = phi + row * nx;
-    for (int i = threadIdx.x; i < nx; i += 256) {
-      const float v = r0[i];
-      if (i + 1 < nx) m[0] = fmaxf(m[0], fabsf(r0[i + 1] - v));
-      if (j + 1 < ny) m[1] = fmaxf(m[1], fabsf(r0[i + nx] - v));
-      if (k + 1 < nz) m[2] = fmaxf(m[2], fabsf(r0[i + plane] - v));
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    float v = m[d];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(max3 + d, __float_as_uint(v));
-  }
+// Slope bounds per block (layout in tacsl_internal.h), from the x-quad node
+// values: first each block's own edges, then the maximum over its neighbours.
+__device__ __forceinline__ float quad_at(const float* q, int i, int j, int k, int ny, int nz) {
+  return q[(int64_t)(i >> 2) * 4 * ny * nz + (int64_t)4 * nz * j + 4 * k + (i & 3)];
+}
+
+__global__ __launch_bounds__(256) void k_block_slopes_raw(const float* __restrict__ q, int nx, int ny, int nz,
+                                                          int sbx, int sby, int sbz, float4* __restrict__ raw) {
+  const int64_t nb = (int64_t)sbx * sby * sbz;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  const int bz = (int)(b % sbz), by = (int)((b / sbz) % sby), bx = (int)(b / ((int64_t)sbz * sby));
+  // nodes of the block's cells
+  const int i0 = bx * kSlopeBlock, i1 = min(i0 + kSlopeBlock, nx - 1);
+  const int j0 = by * kSlopeBlock, j1 = min(j0 + kSlopeBlock, ny - 1);
+  const int k0 = bz * kSlopeBlock, k1 = min(k0 + kSlopeBlock, nz - 1);
+  float mx = 0.f, my = 0.f, mz = 0.f;
+  for (int i = i0; i <= i1; ++i)
+    for (int j = j0; j <= j1; ++j)
+      for (int k = k0; k <= k1; ++k) {
+        const float v = quad_at(q, i, j, k, ny, nz);
+        if (i < i1) mx = fmaxf(mx, fabsf(quad_at(q, i + 1, j, k, ny, nz) - v));
+        if (j < j1) my = fmaxf(my, fabsf(quad_at(q, i, j + 1, k, ny, nz) - v));
+        if (k < k1) mz = fmaxf(mz, fabsf(quad_at(q, i, j, k + 1, ny, nz) - v));
+      }
+  raw[b] = make_float4(mx, my, mz, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_block_slopes_dilate(const float4* __restrict__ raw, int sbx, int sby, int sbz,
+                                                             float4* __restrict__ out) {
+  const int64_t nb = (int64_t)sbx * sby * sbz;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  const int bz = (int)(b % sbz), by = (int)((b / sbz) % sby), bx = (int)(b / ((int64_t)sbz * sby));
+  float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int x = max(bx - 1, 0); x <= min(bx + 1, sbx - 1); ++x)
+    for (int y = max(by - 1, 0); y <= min(by + 1, sby - 1); ++y)
+      for (int z = max(bz - 1, 0); z <= min(bz + 1, sbz - 1); ++z) {
+        const float4 r = raw[((int64_t)x * sby + y) * sbz + z];
+        m.x = fmaxf(m.x, r.x);
+        m.y = fmaxf(m.y, r.y);
+        m.z = fmaxf(m.z, r.z);
+      }
+  out[b] = m;
 }
 
 }  // namespace
@@ -311,10 +338,13 @@ hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* ou
   return hipGetLastError();
 }
 
-hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream) {
-  int64_t blocks = (int64_t)ny * nz;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_grid_slopes, dim3((unsigned)blocks), dim3(256), 0, stream, phi, nx, ny, nz, max3);
+hipError_t launch_block_slopes(const float* phi4, int nx, int ny, int nz, float4* raw, float4* out,
+                               hipStream_t stream) {
+  const int sbx = (int)slope_blocks(nx), sby = (int)slope_blocks(ny), sbz = (int)slope_blocks(nz);
+  const int64_t nb = (int64_t)sbx * sby * sbz;
+  const unsigned blocks = (unsigned)((nb + 255) / 256);
+  hipLaunchKernelGGL(k_block_slopes_raw, dim3(blocks), dim3(256), 0, stream, phi4, nx, ny, nz, sbx, sby, sbz, raw);
+  hipLaunchKernelGGL(k_block_slopes_dilate, dim3(blocks), dim3(256), 0, stream, raw, sbx, sby, sbz, out);
   return hipGetLastError();
 }
 

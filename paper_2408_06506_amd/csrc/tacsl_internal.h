@@ -50,7 +50,6 @@ struct InstStatic {
   uint32_t stride_y;    // bytes between consecutive y
   uint32_t stride_q;    // bytes between consecutive x-pairs
   float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
-  float lip;            // bound on |grad phi| of the trilinear field (edge slopes combined)
   int32_t gid;          // object grid index
   uint32_t mask_off;    // byte offset of the clear-block mask within the prepared grid
   uint32_t mask_sx;     // mask bytes between consecutive x-words (4 W_y W_z)
@@ -195,11 +194,21 @@ struct GradReduceArgs {
 // stride_y = 16 nz, stride_q = stride_y ny, so a 128-byte line holds 4 x-nodes
 // by 8 z-nodes at one y (four times the nodes of a line of (phi, G) records).
 inline int64_t phi_quad_bytes(int64_t nx, int64_t ny, int64_t nz) { return ((nx + 3) / 4) * ny * nz * 16; }
+// Local slope bounds for the sphere steps: per block of 8 x 8 x 8 cells, the
+// largest |phi(node + e_k) - phi(node)| along each axis k over the k-edges of
+// the cells of the block and of its 26 neighbours (float4: x, y, z, unused).
+// Inside a cell each partial derivative of the trilinear field (per grid step)
+// interpolates the cell's edge differences with non-negative weights, so it is
+// bounded by that maximum anywhere within 8 cells of the block.
+constexpr int kSlopeBlock = 8;
+inline int64_t slope_blocks(int64_t n) { return (n - 2) / kSlopeBlock + 1; }
 struct DepthGrid {
   const float* phi;
+  const float4* slope;  // [sbx][sby][sbz]
   uint32_t bytes;
   uint32_t stride_y, stride_q;
-  uint32_t pad_;
+  int32_t sby, sbz;
+  int32_t pad_;
 };
 
 // Tactile depth image: per pad, pixels in 8 x 8 blocks (one wavefront each).
@@ -221,7 +230,7 @@ struct DepthArgs {
 
 hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream);
 hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* out, hipStream_t stream);
-hipError_t launch_grid_slopes(const float* phi, int nx, int ny, int nz, uint32_t* max3, hipStream_t stream);
+hipError_t launch_block_slopes(const float* phi4, int nx, int ny, int nz, float4* raw, float4* out, hipStream_t stream);
 hipError_t launch_depth_image(const DepthArgs& a, hipStream_t stream);
 hipError_t launch_clear_mask(const float* phi, uint32_t* mask, int nx, int ny, int nz, hipStream_t stream);
 hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h,

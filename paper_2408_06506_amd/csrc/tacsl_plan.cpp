@@ -202,6 +202,8 @@ struct tacsl_plan_s {
   float4* grids = nullptr;
   float* d_phi4 = nullptr;                 // node values in x-quad columns (depth image), built on demand
   tacsl::DepthGrid* d_dgrid = nullptr;     // [n_sdf]
+  float4* d_slope = nullptr;               // per-grid block slope bounds (depth image), built with d_phi4
+  int64_t slope_bytes = 0;
   // spatial pad order of the depth image (one unit per pad)
   uint32_t* d_dsp_hist = nullptr;
   uint32_t* d_dsp_cursor = nullptr;
@@ -247,7 +249,7 @@ struct tacsl_plan_s {
                 (ni + 1) * (int64_t)sizeof(int64_t) + (n_env + 1 + ni) * 4 + 4;
     if (obs_n > 0) b += tmpl_T * 4 + ns * obs_n * 4 + ni * 4 + nt * 3 * obs_n * 4;
     if (d_sp_hist) b += 2 * tacsl::kSpatialBins * ns * 4 + ni * 4 + (ns + 1) * 4;
-    if (d_phi4) b += phi4_bytes + ns * (int64_t)sizeof(tacsl::DepthGrid);
+    if (d_phi4) b += phi4_bytes + slope_bytes + ns * (int64_t)sizeof(tacsl::DepthGrid);
     if (d_dsp_hist) b += 2 * tacsl::kSpatialBins * ns * 4 + ni * 4 + (ns + 1) * 4 + (ni + 1) * 8 + ni * 4;
     return b;
   }
@@ -310,6 +312,7 @@ struct tacsl_plan_s {
     dfree(d_env_inst);
     dfree(d_phi4);
     dfree(d_dgrid);
+    dfree(d_slope);
     dfree(d_dsp_hist);
     dfree(d_dsp_cursor);
     dfree(d_dsp_bin);
@@ -637,32 +640,6 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   dfree(d_bad);
   if (e != hipSuccess) return fail(TACSL_ERR_HIP);
   if (bad) return fail(TACSL_ERR_RANGE);
-  // per grid, a bound on |grad phi| of the trilinear field: inside a cell each
-  // partial derivative interpolates the cell's edge slopes along that axis
-  std::vector<float> lip((size_t)d.n_sdf, 0.f);
-  if (d.n_sdf > 0) {
-    uint32_t* d_m = nullptr;
-    if (dalloc(&d_m, (size_t)3 * d.n_sdf) != hipSuccess) return fail(TACSL_ERR_ALLOC);
-    std::vector<uint32_t> m((size_t)3 * d.n_sdf, 0u);
-    bool ok = hipMemset(d_m, 0, m.size() * sizeof(uint32_t)) == hipSuccess;
-    for (int g = 0; ok && g < d.n_sdf; ++g)
-      ok = tacsl::launch_grid_slopes(d.sdf_data + d.sdf_offset[g], d.sdf_dims[3 * g], d.sdf_dims[3 * g + 1],
-                                     d.sdf_dims[3 * g + 2], d_m + 3 * g, nullptr) == hipSuccess;
-    ok = ok && hipMemcpy(m.data(), d_m, m.size() * sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess;
-    dfree(d_m);
-    if (!ok) return fail(TACSL_ERR_HIP);
-    for (int g = 0; g < d.n_sdf; ++g) {
-      double acc = 0.0;
-      for (int a = 0; a < 3; ++a) {
-        float v;
-        std::memcpy(&v, &m[3 * g + a], sizeof(float));
-        const double sl = (double)v / (double)d.sdf_spacing[g];
-        acc += sl * sl;
-      }
-      lip[g] = (float)std::max(std::sqrt(acc) * (1.0 + 1e-5), 1e-6);
-    }
-  }
-
   // static per-pad records
   std::vector<InstStatic> st((size_t)d.n_inst);
   for (int i = 0; i < d.n_inst; ++i) {
@@ -683,7 +660,6 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     s.oy = d.sdf_origin[3 * g + 1];
     s.oz = d.sdf_origin[3 * g + 2];
     s.h = d.sdf_spacing[g];
-    s.lip = lip[g];
     s.gid = g;
     const tacsl::MaskDims md = tacsl::mask_dims(s.nx, s.ny, s.nz);
     s.mask_off = (uint32_t)tacsl::grid_record_bytes(s.nx, s.ny, s.nz);
@@ -842,41 +818,59 @@ int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam) {
     if (!std::isfinite(v)) return TACSL_ERR_RANGE;
   if (!(c.dx > 0.f) || !(c.dy > 0.f) || !(c.gel > 0.f) || !(c.cam_dist >= c.gel)) return TACSL_ERR_RANGE;
   if (!plan->d_phi4 && plan->n_sdf > 0) {
-    // node values in x-quad columns for the ray march (built once)
+    // node values in x-quad columns and block slope bounds for the ray march (built once)
     std::vector<tacsl::DepthGrid> dg((size_t)plan->n_sdf);
-    std::vector<int64_t> base((size_t)plan->n_sdf + 1, 0);
-    for (int g = 0; g < plan->n_sdf; ++g)
-      base[g + 1] = base[g] + tacsl::phi_quad_bytes(plan->sdf_dims[3 * g], plan->sdf_dims[3 * g + 1],
-                                                    plan->sdf_dims[3 * g + 2]) / (int64_t)sizeof(float);
+    std::vector<int64_t> base((size_t)plan->n_sdf + 1, 0), sbase((size_t)plan->n_sdf + 1, 0);
+    int64_t smax = 0;
+    for (int g = 0; g < plan->n_sdf; ++g) {
+      const int64_t nx = plan->sdf_dims[3 * g], ny = plan->sdf_dims[3 * g + 1], nz = plan->sdf_dims[3 * g + 2];
+      base[g + 1] = base[g] + tacsl::phi_quad_bytes(nx, ny, nz) / (int64_t)sizeof(float);
+      const int64_t nb = tacsl::slope_blocks(nx) * tacsl::slope_blocks(ny) * tacsl::slope_blocks(nz);
+      sbase[g + 1] = sbase[g] + nb;
+      smax = std::max(smax, nb);
+    }
     float* d_phi4 = nullptr;
+    float4 *d_slope = nullptr, *d_raw = nullptr;
     tacsl::DepthGrid* d_dg = nullptr;
-    if (hipDeviceSynchronize() != hipSuccess) return TACSL_ERR_HIP;
-    if (dalloc(&d_phi4, (size_t)base[plan->n_sdf]) != hipSuccess || dalloc(&d_dg, dg.size()) != hipSuccess) {
+    auto release = [&]() {
       dfree(d_phi4);
+      dfree(d_slope);
+      dfree(d_raw);
       dfree(d_dg);
+    };
+    if (hipDeviceSynchronize() != hipSuccess) return TACSL_ERR_HIP;
+    if (dalloc(&d_phi4, (size_t)base[plan->n_sdf]) != hipSuccess || dalloc(&d_dg, dg.size()) != hipSuccess ||
+        dalloc(&d_slope, (size_t)sbase[plan->n_sdf]) != hipSuccess || dalloc(&d_raw, (size_t)smax) != hipSuccess) {
+      release();
       return TACSL_ERR_ALLOC;
     }
     bool ok = hipMemset(d_phi4, 0, (size_t)base[plan->n_sdf] * sizeof(float)) == hipSuccess;
     for (int g = 0; ok && g < plan->n_sdf; ++g) {
       const int nx = plan->sdf_dims[3 * g], ny = plan->sdf_dims[3 * g + 1], nz = plan->sdf_dims[3 * g + 2];
       dg[g].phi = d_phi4 + base[g];
+      dg[g].slope = d_slope + sbase[g];
       dg[g].bytes = (uint32_t)((base[g + 1] - base[g]) * (int64_t)sizeof(float));
       dg[g].stride_y = 16u * (uint32_t)nz;
       dg[g].stride_q = dg[g].stride_y * (uint32_t)ny;
+      dg[g].sby = (int32_t)tacsl::slope_blocks(ny);
+      dg[g].sbz = (int32_t)tacsl::slope_blocks(nz);
       dg[g].pad_ = 0;
       ok = tacsl::launch_phi_quad(plan->grids + plan->grid_base[g], nx, ny, nz, d_phi4 + base[g], nullptr) ==
-           hipSuccess;
+               hipSuccess &&
+           tacsl::launch_block_slopes(d_phi4 + base[g], nx, ny, nz, d_raw, d_slope + sbase[g], nullptr) == hipSuccess;
     }
     ok = ok && hipMemcpy(d_dg, dg.data(), dg.size() * sizeof(tacsl::DepthGrid), hipMemcpyHostToDevice) == hipSuccess &&
          hipDeviceSynchronize() == hipSuccess;
+    dfree(d_raw);
     if (!ok) {
-      dfree(d_phi4);
-      dfree(d_dg);
+      release();
       return TACSL_ERR_HIP;
     }
     plan->d_phi4 = d_phi4;
     plan->d_dgrid = d_dg;
+    plan->d_slope = d_slope;
     plan->phi4_bytes = base[plan->n_sdf] * (int64_t)sizeof(float);
+    plan->slope_bytes = sbase[plan->n_sdf] * (int64_t)sizeof(float4);
   }
   if (!plan->d_dsp_order && plan->n_inst > 0) {
     const size_t nb = (size_t)tacsl::kSpatialBins * plan->n_sdf, ni = (size_t)plan->n_inst;

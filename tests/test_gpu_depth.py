@@ -53,7 +53,11 @@ def _check(scene, img_gpu, img_ref, slope, phimin, cam, sel, what, max_mismatch=
     both = hit_ref & hit_gpu
     err = np.abs(z_gpu - z_ref)
     bad = both & (err > tol)
-    assert not bad.any(), f"{what}: {bad.sum()} of {both.sum()} hits off, worst {np.max(err[both] / tol[both]):.3g}x"
+    if bad.any():
+        w = np.unravel_index(np.argmax(np.where(bad, err / tol, 0.0)), bad.shape)
+        detail = (f"pad {int(sel[w[0]])} pixel ({w[1]}, {w[2]}): z_gpu {z_gpu[w]:.9g} z_ref {z_ref[w]:.9g} "
+                  f"slope {slope[w]:.4g} phimin {phimin[w]:.3g}")
+        assert False, f"{what}: {bad.sum()} of {both.sum()} hits off, worst {np.max(err[both] / tol[both]):.3g}x at {detail}"
     only_ref = hit_ref & ~hit_gpu
     only_gpu = hit_gpu & ~hit_ref
     ok_ref = (np.abs(slope) < 0.05) | (np.abs(z_ref) <= tol)
