@@ -187,3 +187,28 @@ def test_depth_single_negative_node(api):
     frac = _check(sc, img.cpu().numpy(), ref, slope, pmin, oc, np.arange(sc.n_inst), "single node", max_mismatch=0.02)
     assert frac > 0.03
     plan.close()
+
+
+@pytest.mark.parametrize("dims,kind", [((37, 44, 29), "sphere"), ((41, 9, 2), "plane")])
+def test_depth_odd_noncubic_grids(api, dims, kind):
+    """Grids whose sizes are not multiples of the 8-cell slope blocks (partial
+    blocks on the far faces, a single cell along z for the thin grid)."""
+    from tests.test_gpu_clear_mask import H, _scene
+    sc, _, _ = _scene(dims, kind, seed=5)
+    ext = H * (np.array(dims) - 1)
+    f = lambda v: float(np.float32(v))
+    rows, cols = 24, 20
+    vals = dict(rows=rows, cols=cols, ortho=0, x0=f(-0.45 * ext[0]), y0=f(-0.45 * ext[1]), dx=f(0.9 * ext[0] / cols),
+                dy=f(0.9 * ext[1] / rows), cam_dist=f(3 * ext[2] + 0.02), gel=f(0.5 * ext[2] + H))
+    oc = oracle.Camera(rows, cols, 0, vals["x0"], vals["y0"], vals["dx"], vals["dy"], vals["cam_dist"], vals["gel"])
+    _say(f"depth {kind} {dims}")
+    plan = api.Plan(sc)
+    plan.set_camera(**vals)
+    status = torch.zeros(1, device=plan.device, dtype=torch.int32)
+    img = plan.depth_image(plan.state(sc.state()), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    ref, slope, pmin = oracle.depth_image(sc, oracle.state64(sc), oc)
+    frac = _check(sc, img.cpu().numpy(), ref, slope, pmin, oc, np.arange(sc.n_inst), f"{kind} {dims}")
+    assert 0.05 < frac < 0.95
+    plan.close()
