@@ -70,6 +70,13 @@ def test_adjoint_differentiation_workload(api):
     st = oracle.state64(sc)
     _, ref, gabs = oracle.grad(sc, st, wa, wb, sel_env=sel, with_abs=True)
     grad_blocks_close(g[sel], ref, 1e-4, what="c5 dual", g_abs=gabs)
+    # the launch shapes the benchmark chooses from (one tile per pad)
+    for tun in (dict(block=256, tile_taxels=0, schedule=0, order=3), dict(block=128, tile_taxels=0, schedule=0, order=5)):
+        _say(f"c5 adjoint {tun}")
+        plan.set_tuning(tun)
+        gt, _ = _gpu_grad(api, plan, sc, wa, wb)
+        grad_blocks_close(gt[sel], ref, 1e-4, what=f"c5 dual {tun}", g_abs=gabs)
+    plan.set_tuning({})
     # central FD of the FP64 loss on the same envs, kink-masked on both sides
     from tests.test_oracle_grad import _perturbed_states
     pert = _perturbed_states(st, sel)

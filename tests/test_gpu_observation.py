@@ -154,7 +154,8 @@ def test_observation_full_size_sampled(api):
     sc = wl.make_c3()
     _say("observation c3")
     bins = wl.scene_observation_bins(sc)
-    plan = api.Plan(sc, dict(block=512, tile_taxels=0, schedule=0, order=3))
+    # the benchmark's launch: the main leg's tuning with one tile per pad
+    plan = api.Plan(sc, dict(block=512, tile_taxels=0, schedule=0, grid=2048, order=5))
     plan.set_observation(bins, 140, scale=SCALE)
     st = plan.state(sc.state())
     obs_o, out_o = plan.observe(st)
