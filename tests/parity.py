@@ -49,7 +49,17 @@ def compare(scene, gpu, ref, D, kn, sel=None, what=""):
     both = (dg > 0) & (dr > 1e-5 * D)
     en = np.linalg.norm(gpu["normal"][:, both] - ref["normal"][:, both], axis=0)
     assert np.all(en <= 1e-4), f"{what} normal: worst {en.max() if en.size else 0:.3g}"
-    # wrench per pad
+    compare_wrench(scene, gpu["wrench"], ref, D, kn, sel=sel, gpu_depth=dg, what=what)
+
+
+def compare_wrench(scene, wrench, ref, D, kn, sel=None, gpu_depth=None, extra_contacts=0, what=""):
+    """Per-pad wrench bounds (module docstring); the taxels in contact on the
+    GPU side count into the floor when ``gpu_depth`` is given.  Without it,
+    ``extra_contacts`` taxels per pad (at the largest |x| of the pad) may be in
+    contact on the GPU side alone, within the depth floor of the surface."""
+    sel = np.arange(scene.n_inst) if sel is None else np.asarray(sel)
+    dr = ref["depth"]
+    dg = dr if gpu_depth is None else gpu_depth
     counts = np.diff(scene.tmpl_offset)[scene.inst_tmpl[sel]]
     starts = np.concatenate([[0], np.cumsum(counts)])
     f = ref["fn"] + ref["ft"]
@@ -62,10 +72,10 @@ def compare(scene, gpu, ref, D, kn, sel=None, what=""):
         xn = np.linalg.norm(x, axis=0)
         sl = slice(starts[j], starts[j + 1])
         c = either[sl]
-        sF = fmag[sl].sum() + 1e4 * floor * c.sum()
-        sT = (xn * fmag[sl]).sum() + 1e4 * floor * xn[c].sum()
-        dF = np.abs(gpu["wrench"][j, :3] - ref["wrench"][j, :3]).max()
-        dT = np.abs(gpu["wrench"][j, 3:] - ref["wrench"][j, 3:]).max()
+        sF = fmag[sl].sum() + 1e4 * floor * (c.sum() + extra_contacts)
+        sT = (xn * fmag[sl]).sum() + 1e4 * floor * (xn[c].sum() + extra_contacts * xn.max(initial=0.0))
+        dF = np.abs(wrench[j, :3] - ref["wrench"][j, :3]).max()
+        dT = np.abs(wrench[j, 3:] - ref["wrench"][j, 3:]).max()
         assert dF <= 1e-4 * sF + 1e-30, f"{what} wrench F pad {i}: {dF} > 1e-4 * {sF}"
         assert dT <= 1e-4 * sT + 1e-30, f"{what} wrench torque pad {i}: {dT} > 1e-4 * {sT}"
 

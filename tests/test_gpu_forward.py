@@ -239,3 +239,44 @@ def test_rejected_tuning_keeps_the_plan_usable(api):
     for k in ("depth", "normal", "fn", "ft", "wrench"):
         assert torch.equal(out[k], ref[k]), k
     plan.close()
+
+
+def test_batched_uneven_full_size(api):
+    """4096 envs, 8192 pads of three resolutions on 24 grids (64/128/256^3),
+    100 substeps in one HIP graph with the kind of launch the benchmark
+    times (persistent dynamic queue): per-taxel outputs of substeps 0, 1, 49
+    and 99 and the wrenches of all 100 substeps on 64 sampled pads."""
+    from tests.parity import compare_wrench
+    sc = wl.make_c4()
+    S = sc.obj_pose_steps.shape[0]
+    _say("c4 batched plan")
+    plan = api.Plan(sc, dict(block=512, tile_taxels=1024, schedule=2, grid=1024, order=0))
+    states = [plan.state(sc.state(s)) for s in range(S)]
+    out = plan.new_outputs()
+    wrench = torch.empty(S, sc.n_inst, 6, device=plan.device)
+    graph = api.SubstepGraph(plan, states, [dict(out, wrench=wrench[s]) for s in range(S)])
+    _say("c4 graph launch")
+    graph.launch()
+    torch.cuda.synchronize()
+    sel = np.sort(np.random.default_rng(21).choice(sc.n_inst, 64, replace=False)).astype(np.int32)
+    off = plan.offsets()
+    assert off.tolist() == oracle.offsets(sc).tolist()
+    rows = torch.as_tensor(rows_of(off, sel))
+    ws = wrench[:, torch.as_tensor(sel, dtype=torch.long)].cpu().numpy().astype(np.float64)
+    for s in range(S):
+        ref = oracle.force_field(sc, oracle.state64(sc, step=s), sel=sel)
+        if s == S - 1:
+            g = gpu_outputs_np(out, rows=rows)
+            g["wrench"] = ws[s]
+            compare(sc, g, ref, D=2e-3, kn=KN, sel=sel, what=f"c4 graph substep {s}")
+        else:
+            compare_wrench(sc, ws[s], ref, D=2e-3, kn=KN, sel=sel, extra_contacts=8, what=f"c4 graph substep {s}")
+        if s in (0, 1, 49):
+            o = plan.forward(states[s])
+            torch.cuda.synchronize()
+            g = gpu_outputs_np(o, rows=rows)
+            g["wrench"] = o["wrench"][torch.as_tensor(sel, dtype=torch.long)].cpu().numpy().astype(np.float64)
+            compare(sc, g, ref, D=2e-3, kn=KN, sel=sel, what=f"c4 eager substep {s}")
+            assert np.array_equal(g["wrench"], ws[s])  # graph replay = eager launch
+    graph.close()
+    plan.close()
