@@ -85,8 +85,9 @@ typedef enum {
  *   tmpl_xyz  device [3][T_tmpl] FP32 SoA taxel positions in the pad frame
  *             (T_tmpl = tmpl_offset[n_tmpl]); the pad plane faces +z towards the object
  *   sdf_dims  host [n_sdf][3]  nodes per axis (nx, ny, nz), each >= 2; the plan's copy
- *             (16 bytes per node, x rounded up to even) must stay below 4 GiB, i.e. up to ~645^3,
- *             and 32 ny nz below 2^24 (ny nz < 524288, e.g. 724 x 724); else TACSL_ERR_UNSUPPORTED
+ *             (16 bytes per node, x and y rounded up to even, plus a ~0.1% bit mask) must stay
+ *             below 4 GiB, i.e. up to 644^3, and 64 ceil(ny/2) nz below 2^24 (ceil(ny/2) nz < 262144,
+ *             e.g. 724 x 723); else TACSL_ERR_UNSUPPORTED
  *   sdf_origin host [n_sdf][3] position of node (0,0,0) in the object frame
  *   sdf_spacing host [n_sdf]   isotropic node spacing h > 0
  *   sdf_offset host [n_sdf]    element offset of each grid in sdf_data

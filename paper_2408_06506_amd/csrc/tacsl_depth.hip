@@ -271,12 +271,13 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
 __global__ __launch_bounds__(256) void k_phi_quad(const float4* __restrict__ grid, int nx, int ny, int nz,
                                                   float* __restrict__ out) {
   const int64_t rows = (int64_t)ny * nz;
-  const uint32_t sy4 = 32u * (uint32_t)nz, sq4 = sy4 * (uint32_t)ny;      // (phi, G) layout strides
+  const uint32_t sy4 = 64u * (uint32_t)nz, sq4 = sy4 * (uint32_t)((ny + 1) / 2);  // (phi, G) layout strides
   const int64_t qy = (int64_t)nz * 4, qq = qy * ny;                      // x-quad strides in floats
   for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
     const int j = (int)(row / nz), k = (int)(row % nz);
     for (int i = threadIdx.x; i < nx; i += 256) {
-      const uint32_t src = (uint32_t)(i >> 1) * sq4 + (uint32_t)j * sy4 + (uint32_t)k * 32u + (uint32_t)(i & 1) * 16u;
+      const uint32_t src = (uint32_t)(i >> 1) * sq4 + (uint32_t)(j >> 1) * sy4 + (uint32_t)k * 64u +
+                           (uint32_t)(j & 1) * 32u + (uint32_t)(i & 1) * 16u;
       const float v = reinterpret_cast<const float*>(reinterpret_cast<const char*>(grid) + src)[0];
       out[(int64_t)(i >> 2) * qq + (int64_t)j * qy + (int64_t)k * 4 + (i & 3)] = v;
     }

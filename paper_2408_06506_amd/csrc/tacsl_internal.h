@@ -6,15 +6,16 @@
 
 namespace tacsl {
 
-// Prepared grid ("x-pair columns"): one float4 record per node,
+// Prepared grid ("2 x 2 columns"): one float4 record per node,
 // (phi, G_x, G_y, G_z) with G the nodal finite-difference gradient (central
 // inside, one-sided on the faces).  Node (i, j, k) is stored at byte
-//   (i >> 1) * stride_q + j * stride_y + k * 32 + (i & 1) * 16,
-//   stride_y = 32 nz,  stride_q = stride_y ny,
-// so one 128-byte line holds 2 x-nodes by 4 z-nodes at one y: the eight
-// corners of a cell are reached from 2 per-lane offsets (x and x+1), with the
-// y step as a scalar offset and the z step as an immediate offset.
-inline int64_t grid_record_bytes(int64_t nx, int64_t ny, int64_t nz) { return ((nx + 1) / 2) * ny * nz * 32; }
+//   (i >> 1) * stride_q + (j >> 1) * stride_y + k * 64 + (j & 1) * 32 + (i & 1) * 16,
+//   stride_y = 64 nz,  stride_q = stride_y * ceil(ny / 2),
+// so each 2 x 2 column of nodes runs along z in 64-byte slabs and a 128-byte
+// line holds a 2 x 2 x 2 brick (for even nz): fewer distinct lines per
+// wavefront of taxels than 2 x 4 (x, z) patches.  The z step of a cell is an
+// immediate offset (+64).
+inline int64_t grid_record_bytes(int64_t nx, int64_t ny, int64_t nz) { return ((nx + 1) / 2) * ((ny + 1) / 2) * nz * 64; }
 
 // Clear-block mask, stored after the records of each prepared grid: one bit
 // per block of 2 x 2 x 2 cells (block b spans nodes 2b .. 2b + 2 per axis,
@@ -47,7 +48,7 @@ struct InstStatic {
   int32_t env;          // environment of the pad
   int32_t count;        // taxels on the pad
   uint32_t grid_bytes;  // bytes of the prepared grid (< 2^32)
-  uint32_t stride_y;    // bytes between consecutive y
+  uint32_t stride_y;    // bytes between consecutive y-pairs
   uint32_t stride_q;    // bytes between consecutive x-pairs
   float ox, oy, oz, h;  // node (0,0,0) in the object frame, node spacing
   int32_t gid;          // object grid index

@@ -8,7 +8,7 @@
 //
 // Kernels
 //   k_prepare_grid  once per plan: node value + nodal finite-difference
-//                   gradient as one float4 record per node, in x-pair columns.
+//                   gradient as one float4 record per node, in 2 x 2 columns.
 //   k_prologue      per pad, FP64: relative pose and twist, folded into an
 //                   affine map taxel -> grid coordinates (FP32 record).
 //   k_force_fwd     per tile of taxels: the whole per-taxel path, SoA stores,
@@ -22,8 +22,9 @@
 // contiguous bytes per wave; each of the eight corners of a taxel's cell is
 // one 16-byte record (value and gradient), so a taxel costs eight gather
 // instructions (fewer, wider gathers are what the vector L1 handles best);
-// records are laid out so a 128-byte line holds a 2 x 4 patch of nodes (a
-// third fewer lines per taxel than x-fastest rows) and are fetched through a
+// records are laid out so a 128-byte line holds a 2 x 2 x 2 brick of nodes
+// (a wavefront's gathers touch a third fewer lines than with x-fastest rows)
+// and are fetched through a
 // bounds-checked buffer resource (an out-of-range offset reads zeros instead
 // of faulting); per-pad constants live in scalar registers; reductions are
 // fixed-order (deterministic, no float atomics).
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(256) void k_clear_mask(const float* __restrict__ ph
 
 // ---------------------------------------------------------------------------
 // SDF preparation: (phi, G) per node, G = nodal finite differences (central
-// inside, one-sided on the faces), stored in the x-pair column layout.
+// inside, one-sided on the faces), stored in the 2 x 2 column layout.
 // Counts non-finite node values.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_prepare_grid(const float* __restrict__ phi, float4* __restrict__ out,
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_prepare_grid(const float* __restrict__ 
     const float gz = (phi[((int64_t)kh * ny + j) * nx + i] - phi[((int64_t)kl * ny + j) * nx + i]) /
                      ((float)(kh - kl) * h);
     if (!isfinite(p)) atomicAdd(bad, 1u);
-    const int64_t rec = ((int64_t)(i >> 1) * ny + j) * nz * 2 + (int64_t)k * 2 + (i & 1);
+    const int64_t rec = ((int64_t)(i >> 1) * ((ny + 1) / 2) + (j >> 1)) * nz * 4 + (int64_t)k * 4 + (j & 1) * 2 + (i & 1);
     out[rec] = make_float4(p, gx, gy, gz);
   }
 }
@@ -330,23 +331,25 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
     const uint32_t word = __builtin_amdgcn_raw_buffer_load_b32(rs, mo, 0u, 0);
     if ((word >> ((bx & 3u) | ((by & 3u) << 2) | ((bz & 1u) << 4))) & 1u) return;
   }
-  // per-lane offsets of the two x-nodes; y steps are scalar, z steps
-  // immediate.  Plan creation keeps stride_q = 32 ny nz below 2^24 (and so
-  // stride_y and the cell indices), so the products fit the full-rate 24-bit
-  // multiplier.
-  const uint32_t yz = __umul24((uint32_t)cy, st.stride_y) + (uint32_t)cz * 32u;
-  const uint32_t x0 = (uint32_t)cx, x1 = x0 + 1u;
-  const uint32_t o0 = __umul24(x0 >> 1, st.stride_q) + (x0 & 1u) * 16u + yz;
-  const uint32_t o1 = __umul24(x1 >> 1, st.stride_q) + (x1 & 1u) * 16u + yz;
-  const uint32_t sy = st.stride_y;
-  f.c[0] = load_node(rs, o0, 0u);
-  f.c[1] = load_node(rs, o1, 0u);
-  f.c[2] = load_node(rs, o0, sy);
-  f.c[3] = load_node(rs, o1, sy);
-  f.c[4] = load_node(rs, o0 + 32u, 0u);
-  f.c[5] = load_node(rs, o1 + 32u, 0u);
-  f.c[6] = load_node(rs, o0 + 32u, sy);
-  f.c[7] = load_node(rs, o1 + 32u, sy);
+  // per-lane offsets of the four (x, y) corner columns; the z step is an
+  // immediate offset.  Plan creation keeps stride_q = 64 ceil(ny / 2) nz below
+  // 2^24 (and so stride_y and the cell indices), so the products fit the
+  // full-rate 24-bit multiplier.
+  const uint32_t x0 = (uint32_t)cx, x1 = x0 + 1u, y0 = (uint32_t)cy, y1 = y0 + 1u;
+  const uint32_t z = (uint32_t)cz * 64u;
+  const uint32_t ox0 = __umul24(x0 >> 1, st.stride_q) + (x0 & 1u) * 16u + z;
+  const uint32_t ox1 = __umul24(x1 >> 1, st.stride_q) + (x1 & 1u) * 16u + z;
+  const uint32_t oy0 = __umul24(y0 >> 1, st.stride_y) + (y0 & 1u) * 32u;
+  const uint32_t oy1 = __umul24(y1 >> 1, st.stride_y) + (y1 & 1u) * 32u;
+  const uint32_t o00 = ox0 + oy0, o10 = ox1 + oy0, o01 = ox0 + oy1, o11 = ox1 + oy1;
+  f.c[0] = load_node(rs, o00, 0u);
+  f.c[1] = load_node(rs, o10, 0u);
+  f.c[2] = load_node(rs, o01, 0u);
+  f.c[3] = load_node(rs, o11, 0u);
+  f.c[4] = load_node(rs, o00 + 64u, 0u);
+  f.c[5] = load_node(rs, o10 + 64u, 0u);
+  f.c[6] = load_node(rs, o01 + 64u, 0u);
+  f.c[7] = load_node(rs, o11 + 64u, 0u);
   const float4* c = f.c;
   f.phi = tri(c[0].x, c[1].x, c[2].x, c[3].x, c[4].x, c[5].x, c[6].x, c[7].x, f.tx, f.ty, f.tz);
   if (!(f.phi < 0.f)) return;

@@ -55,7 +55,7 @@ int validate(const tacsl_scene_desc* d) {
     const int32_t* n = d->sdf_dims + 3 * g;
     if (n[0] < 2 || n[1] < 2 || n[2] < 2) return TACSL_ERR_SHAPE;
     if (tacsl::prepared_grid_bytes(n[0], n[1], n[2]) > kMaxGridBytes) return TACSL_ERR_UNSUPPORTED;
-    if (int64_t(32) * n[1] * n[2] > kMaxPairStride) return TACSL_ERR_UNSUPPORTED;
+    if (int64_t(64) * ((n[1] + 1) / 2) * n[2] > kMaxPairStride) return TACSL_ERR_UNSUPPORTED;
     const float h = d->sdf_spacing[g];
     if (!(h > 0.f) || !std::isfinite(h)) return TACSL_ERR_RANGE;
     for (int a = 0; a < 3; ++a)
@@ -608,7 +608,7 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
   for (int i = 0; i < d.n_inst; ++i) p->inst_off[i + 1] = p->inst_off[i] + tmpl_count(d, i);
   p->T = p->inst_off[d.n_inst];
 
-  // prepared SDF pool: per grid, (phi, G) float4 records in x-pair columns and
+  // prepared SDF pool: per grid, (phi, G) float4 records in 2 x 2 columns and
   // the clear-block mask after them
   std::vector<int64_t> gbase((size_t)d.n_sdf + 1, 0);
   for (int g = 0; g < d.n_sdf; ++g)
@@ -654,8 +654,8 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
     s.env = d.inst_env[i];
     s.count = (int32_t)tmpl_count(d, i);
     s.grid_bytes = (uint32_t)((gbase[g + 1] - gbase[g]) * (int64_t)sizeof(float4));
-    s.stride_y = 32u * (uint32_t)s.nz;
-    s.stride_q = s.stride_y * (uint32_t)s.ny;
+    s.stride_y = 64u * (uint32_t)s.nz;
+    s.stride_q = s.stride_y * (uint32_t)((s.ny + 1) / 2);
     s.ox = d.sdf_origin[3 * g];
     s.oy = d.sdf_origin[3 * g + 1];
     s.oz = d.sdf_origin[3 * g + 2];

@@ -100,23 +100,26 @@ def test_invalid_descriptions_return_codes():
     so = sc.sdf_offset.copy()
     so[0] = -5
     assert api.validate_scene(_mut(sc, sdf_offset=so)) == -3
-    # the plan's grid copy (16 B per node, x rounded up to even) must stay below 4 GiB
+    # the plan's grid copy (16 B per node, x and y rounded up to even, plus
+    # one bit per 2x2x2-cell block in 32-bit words of 4x4x2 blocks) must stay
+    # below 4 GiB
     def copy_bytes(n):
-        n = [int(v) for v in n]
-        return ((n[0] + 1) // 2) * n[1] * n[2] * 32
+        nx, ny, nz = (int(v) for v in n)
+        mask = ((nx // 2 + 3) // 4) * ((ny // 2 + 3) // 4) * ((nz // 2 + 1) // 2) * 4
+        return ((nx + 1) // 2) * ((ny + 1) // 2) * nz * 64 + (mask + 15) // 16 * 16
     dims = sc.sdf_dims.copy()
     dims[0] = (646, 646, 646)
     assert copy_bytes(dims[0]) >= 2 ** 32
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == -6
-    dims[0] = (644, 645, 645)
+    dims[0] = (644, 644, 644)
     assert copy_bytes(dims[0]) < 2 ** 32
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == 0
-    # one x-pair slab (32 ny nz bytes) must stay below 2^24 bytes
+    # one x-pair slab (64 ceil(ny/2) nz bytes) must stay below 2^24 bytes
     dims[0] = (2, 800, 800)
-    assert copy_bytes(dims[0]) < 2 ** 32 and 32 * 800 * 800 >= 2 ** 24
+    assert copy_bytes(dims[0]) < 2 ** 32 and 64 * 400 * 800 >= 2 ** 24
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == -6
     dims[0] = (4, 724, 723)
-    assert 32 * 724 * 723 < 2 ** 24
+    assert 64 * 362 * 723 < 2 ** 24
     assert api.validate_scene(_mut(sc, sdf_dims=dims)) == 0
     # counts
     assert api.validate_scene(_mut(sc, n_env=-1)) == -2
