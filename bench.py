@@ -45,32 +45,34 @@ def log(msg):
 FOOTPRINT = os.path.join(ROOT, "tests", "golden", "sdf_footprint.json")
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_force_fwd_roofline_8192x2x80x100_256.md")
+# rocprofv3 summaries of the forward kernel on the roofline workload, one per profiled launch shape
+PROFILE_GLOB = os.path.join(ROOT, "profiles", "k_force_fwd_roofline_8192x2x80x100_256*.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2408_06506_amd", "csrc", f)
                   for f in ("tacsl_kernels.hip", "tacsl_device.h", "tacsl_internal.h")]
 
 
 def measured_traffic(tuning):
-    """HBM bytes per launch of the forward kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the kernel
-    sources or the tuning differ from those the counters were taken with."""
+    """HBM bytes per launch of the forward kernel from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated) taken with this tuning,
+    or None when none matches the tuning and the current kernel sources."""
+    import glob
     import hashlib
-    try:
-        rec = {}
-        for line in open(PROFILE):
-            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha1", "tuning"):
-                k, v = line.split(":", 1)
-                rec[k] = v.strip()
-        h = hashlib.sha1()
-        for f in KERNEL_SOURCES:
-            h.update(open(f, "rb").read())
-        if rec.get("kernel_source_sha1") != h.hexdigest()[:16]:
-            return None
-        if json.loads(rec["tuning"]) != dict(tuning):
-            return None
-        return float(rec["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()[:16]
+    for path in sorted(glob.glob(PROFILE_GLOB)):
+        try:
+            rec = {}
+            for line in open(path):
+                if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha1", "tuning"):
+                    k, v = line.split(":", 1)
+                    rec[k] = v.strip()
+            if rec.get("kernel_source_sha1") == sha and json.loads(rec["tuning"]) == dict(tuning):
+                return float(rec["traffic_bytes_per_launch"])
+        except (OSError, KeyError, ValueError):
+            continue
+    return None
 
 
 def sdf_footprint_nodes(key, scene):
