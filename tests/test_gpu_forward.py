@@ -143,18 +143,20 @@ def test_roofline_shape_sampled(api):
     frac = (d > 0).float().mean().item()
     print(f"c3 realized contact fraction {frac:.4f}")
     assert 0.62 < frac < 0.75
-    # the launch the benchmark times (autotuned on MI355X): per-taxel outputs
-    # bitwise those of the default launch, wrenches (summed per tile) against
-    # the oracle
-    _say("c3 benchmark launch")
-    plan.set_tuning(dict(block=512, tile_taxels=4096, schedule=0, grid=2048, order=5))
-    out2 = plan.forward(plan.state(sc.state()))
-    torch.cuda.synchronize()
-    for k in ("depth", "normal", "fn", "ft"):
-        assert torch.equal(out[k], out2[k]), k
-    g2 = gpu_outputs_np(out2, rows=torch.as_tensor(rows))
-    g2["wrench"] = out2["wrench"][torch.as_tensor(sel, dtype=torch.long)].cpu().numpy().astype(np.float64)
-    compare(sc, g2, ref, D=2e-3, kn=KN, sel=sel, what="c3 benchmark launch")
+    # the launches the benchmark times (autotuned on MI355X, either of two
+    # within noise): per-taxel outputs bitwise those of the default launch,
+    # wrenches (summed per tile) against the oracle
+    for tile in (4096, 0):
+        _say(f"c3 benchmark launch, tile {tile}")
+        plan.set_tuning(dict(block=512, tile_taxels=tile, schedule=0, grid=2048, order=5))
+        out2 = plan.forward(plan.state(sc.state()))
+        torch.cuda.synchronize()
+        for k in ("depth", "normal", "fn", "ft"):
+            assert torch.equal(out[k], out2[k]), (k, tile)
+        g2 = gpu_outputs_np(out2, rows=torch.as_tensor(rows))
+        g2["wrench"] = out2["wrench"][torch.as_tensor(sel, dtype=torch.long)].cpu().numpy().astype(np.float64)
+        compare(sc, g2, ref, D=2e-3, kn=KN, sel=sel, what=f"c3 benchmark launch, tile {tile}")
+        del out2
     plan.close()
 
 
