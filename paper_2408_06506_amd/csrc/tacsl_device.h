@@ -30,10 +30,24 @@ __device__ __forceinline__ void put(float* base, uint32_t k, float v) {
   __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (k << 2)));
 }
 
+// Sum over the 64 lanes of a wavefront (all lanes active), in registers:
+// data-parallel-primitive moves within quads, half-rows and rows, then the
+// row broadcasts of lanes 15 and 31; lane 63 ends with the total, returned
+// to every lane.  The order of the additions is fixed.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int t = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF, false);
+  return v + __builtin_bit_cast(float, t);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]: quad sums
+  v = dpp_add<0x141, 0xF>(v);  // row_half_mirror: 8-lane sums
+  v = dpp_add<0x140, 0xF>(v);  // row_mirror: 16-lane (row) sums
+  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
