@@ -189,6 +189,8 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
                        fmaf(x.A[6], px, fmaf(x.A[7], py, x.b[2]))};
   const float uz[3] = {fmaf(x.A[0], ex, fmaf(x.A[1], ey, x.A[2])), fmaf(x.A[3], ex, fmaf(x.A[4], ey, x.A[5])),
                        fmaf(x.A[6], ex, fmaf(x.A[7], ey, x.A[8]))};
+  // one division per axis; the box clipping and the step cap multiply by it
+  const float iuz[3] = {1.f / uz[0], 1.f / uz[1], 1.f / uz[2]};
   float zlo = -a.gel, zhi = 0.f;
   const int n[3] = {st.nx, st.ny, st.nz};
 #pragma unroll
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
       if (!(u0[k] >= 0.f && u0[k] <= n1)) zhi = -INFINITY;
       continue;
     }
-    const float za = -u0[k] / uz[k], zb = (n1 - u0[k]) / uz[k];
+    const float za = -u0[k] * iuz[k], zb = (n1 - u0[k]) * iuz[k];
     zlo = fmaxf(zlo, fminf(za, zb));
     zhi = fminf(zhi, fmaxf(za, zb));
   }
@@ -210,8 +212,8 @@ __global__ __launch_bounds__(256) void k_depth_image(const DepthArgs a) {
     rc.cy = -1;
     rc.cz = -1;
     const float au[3] = {fabsf(uz[0]), fabsf(uz[1]), fabsf(uz[2])};
-    const float zcap = 7.f / fmaxf(au[0], fmaxf(au[1], au[2]));  // at most 7 cells along any axis
-    const float iuz[3] = {1.f / uz[0], 1.f / uz[1], 1.f / uz[2]};
+    // at most 7 cells along any axis (1 / |uz| is infinite on an axis the ray does not move along)
+    const float zcap = 7.f * fminf(fabsf(iuz[0]), fminf(fabsf(iuz[1]), fabsf(iuz[2])));
     float z = zlo;
     float u[3] = {fmaf(z, uz[0], u0[0]), fmaf(z, uz[1], u0[1]), fmaf(z, uz[2], u0[2])};
     ray_cell(st, g, rs, rc, u[0], u[1], u[2]);
