@@ -140,10 +140,147 @@ def run_main(args, torch, api, wl, autotune):
                 contact=contact)
 
 
-def run_cpu_baseline(sc, budget_threads):
+def run_tiny(args, torch, api, wl):
+    """The tiny ball case: 1 env, 1 pad of 20x25 taxels, sphere r = 10 mm at
+    64^3 / 0.5 mm, 100 seeded steps (each step its own pose and velocity).
+    Latency-bound: reported as microseconds per step, for one call per step
+    (host launch included) and for the 100 steps captured in one HIP graph."""
+    scenes = [wl.make_c1(step) for step in range(100)]
+    plan = api.Plan(scenes[0])
+    states = [plan.state(s.state()) for s in scenes]
+    out = plan.new_outputs()
+    for st in states[:10]:
+        plan.forward(st, out)
+    torch.cuda.synchronize()
+    plan.timer_start(len(states))
+    t0 = time.perf_counter()
+    for st in states:
+        plan.forward(st, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = plan.timer_read(len(states))
+    plan.timer_start(0)
+    outs = [plan.new_outputs() for _ in states]
+    g = api.SubstepGraph(plan, states, outs)
+    g.launch()
+    torch.cuda.synchronize()
+    reps = 20
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.launch()
+    b.record()
+    torch.cuda.synchronize()
+    us_graph = a.elapsed_time(b) * 1e3 / (reps * len(states))
+    g.close()
+    plan.close()
+    T = scenes[0].n_taxels
+    res = {"workload": "tiny ball: 1 env x 1 pad 20x25 taxels, sphere r=10 mm at 64^3 / 0.5 mm, 100 seeded steps",
+           "taxels_per_step": T, "us_per_step_eager": wall * 1e6 / len(states),
+           "us_per_step_graph": us_graph, "kernel_avg_us": float(np.mean(kms)) * 1e3,
+           "taxel_evals_per_s_graph": T / (us_graph * 1e-6)}
+    log(f"tiny: {res['us_per_step_eager']:.1f} us/step eager, {us_graph:.2f} us/step in a graph, "
+        f"kernel {res['kernel_avg_us']:.2f} us")
+    return res, scenes
+
+
+def run_scale(args, torch, api, wl, autotune):
+    """The plain method at scale: 1024 envs x 2 pads x 40x50 taxels, five
+    objects at 128^3, penetration U[0, 2] mm; autotuned; throughput and the
+    forward kernel against the HBM roofline (same byte count as the main leg)."""
+    sc = wl.make_c2()
+    plan = api.Plan(sc)
+    st = plan.state(sc.state())
+    out = plan.new_outputs()
+    if not args.no_tune:
+        autotune.autotune(plan, sc, st, out, reps=5, tag="c2")
+    for _ in range(args.warmup):
+        plan.forward(st, out)
+    steps = max(20, args.steps)
+    plan.timer_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forward(st, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = float(np.mean(plan.timer_read(steps)))
+    tun = plan.tuning
+    plan.close()
+    V = sdf_footprint_nodes("scale_1024x2x40x50_128", sc)
+    B = algorithmic_bytes(sc, V)
+    res = {"workload": "plain scale: 1024 envs x 2 pads x 40x50 taxels, 5 objects at 128^3",
+           "taxels_per_step": sc.n_taxels, "ms_per_step": wall * 1e3 / steps,
+           "taxel_evals_per_s": sc.n_taxels * steps / wall, "tuning": tun, "kernel": "k_force_fwd",
+           "kernel_avg_ms": kms, "algorithmic_bytes_per_launch": B,
+           "achieved_GBps": B / (kms * 1e-3) / 1e9, "frac_of_hbm_peak": B / (kms * 1e-3) / HBM_PEAK}
+    log(f"scale: {res['ms_per_step']:.4f} ms/step, kernel {kms:.4f} ms, frac {res['frac_of_hbm_peak']:.3f}")
+    return res, sc
+
+
+def host_cores():
+    """Host CPUs as the OS reports them: (os.cpu_count(), CPUs this process may run on)."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = os.cpu_count() or 1
+    return os.cpu_count() or 1, aff
+
+
+def oracle_timings(scenes, threads):
+    """The oracle on the other workloads, each on `threads` threads (plus one
+    thread for the tiny case): the tiny case and the plain scale in full, the
+    differentiation workload's forward and its dual-number gradient (16
+    directions) in full, the batched uneven workload at substeps 0, 1, 49, 99."""
+    import oracle
+    res = {}
+    tiny = scenes.get("tiny")
+    if tiny:
+        for nt in (1, threads):
+            t0 = time.perf_counter()
+            for s in tiny:
+                oracle.force_field(s, oracle.state64(s), nthreads=nt)
+            dt = time.perf_counter() - t0
+            n = sum(s.n_taxels for s in tiny)
+            res[f"tiny_{nt}_threads"] = {"steps": len(tiny), "us_per_step": dt * 1e6 / len(tiny),
+                                         "taxel_evals_per_s": n / dt}
+    for key in ("scale", "differentiation"):
+        s = scenes.get(key)
+        if s is None:
+            continue
+        st = oracle.state64(s)
+        t0 = time.perf_counter()
+        oracle.force_field(s, st, nthreads=threads)
+        dt = time.perf_counter() - t0
+        res[key] = {"taxels": s.n_taxels, "s_per_step": dt, "taxel_evals_per_s": s.n_taxels / dt}
+        if key == "differentiation":
+            from paper_2408_06506_amd import workloads as wl
+            wa, wb = wl.loss_weights(s.n_taxels, 5)
+            t0 = time.perf_counter()
+            oracle.grad(s, st, wa, wb, nthreads=threads)
+            dt = time.perf_counter() - t0
+            res["differentiation_dual_gradient"] = {"taxels": s.n_taxels, "s_per_gradient": dt,
+                                                    "taxel_evals_per_s": s.n_taxels / dt}
+    s = scenes.get("batched")
+    if s is not None:
+        sub = {}
+        for step in (0, 1, 49, 99):
+            if step >= s.obj_pose_steps.shape[0]:
+                continue
+            st = oracle.state64(s, step=step)
+            t0 = time.perf_counter()
+            oracle.force_field(s, st, nthreads=threads)
+            sub[str(step)] = time.perf_counter() - t0
+        res["batched_substeps"] = {"taxels_per_substep": s.n_taxels, "s_per_substep": sub,
+                                   "taxel_evals_per_s": s.n_taxels * len(sub) / sum(sub.values())}
+    return res
+
+
+def run_cpu_baseline(sc, budget_threads, scenes=None):
     import oracle
     st = oracle.state64(sc)
-    threads = max(1, min(budget_threads, os.cpu_count() or 1))
+    n_cpu, n_aff = host_cores()
+    threads = max(1, min(budget_threads, n_aff))
     sel1 = np.arange(0, sc.n_inst, 8, dtype=np.int32)
     t0 = time.perf_counter()
     oracle.force_field(sc, st, sel=sel1, nthreads=1)
@@ -157,11 +294,16 @@ def run_cpu_baseline(sc, budget_threads):
         oracle.force_field(sc, st, nthreads=threads)
         reps.append(time.perf_counter() - t0)
     tN = float(np.median(reps))
-    return {"value": sc.n_taxels / tN, "unit": "taxel-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 C++ oracle (g++ -O2, OpenMP over pads): the full roofline-shape step "
-                      f"({sc.n_taxels} taxels) on {threads} threads, median of {len(reps)} runs {tN:.2f} s; "
-                      f"1 thread on every 8th pad ({n1} taxels) in {t1:.2f} s = {n1 / t1:.3e} taxel-evals/s",
-            "single_thread_value": n1 / t1}
+    res = {"value": sc.n_taxels / tN, "unit": "taxel-evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 C++ oracle (g++ -O2, OpenMP over pads): the full roofline-shape step "
+                     f"({sc.n_taxels} taxels) on {threads} threads, median of {len(reps)} runs {tN:.2f} s; "
+                     f"1 thread on every 8th pad ({n1} taxels) in {t1:.2f} s = {n1 / t1:.3e} taxel-evals/s",
+           "single_thread_value": n1 / t1,
+           "host": {"os_cpu_count": n_cpu, "affinity_cpus": n_aff, "threads_used": threads,
+                    "thread_cap": budget_threads}}
+    if scenes:
+        res["per_workload"] = oracle_timings(scenes, threads)
+    return res
 
 
 def run_batched_vs_plain(args, torch, api, wl, autotune):
@@ -457,6 +599,8 @@ def main():
     ap.add_argument("--no-observation", action="store_true")
     ap.add_argument("--no-depth", action="store_true")
     ap.add_argument("--no-nonlinear", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true")
+    ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--threads", type=int, default=16)
     ap.add_argument("--tuning", type=str, default=None,
@@ -473,6 +617,8 @@ def main():
         args.no_observation = True
         args.no_depth = True
         args.no_nonlinear = True
+        args.no_tiny = True
+        args.no_scale = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (environments shard "
               f"across GPUs without exchange; only the single-GPU shard is built here).", file=sys.stderr)
@@ -521,13 +667,24 @@ def main():
     depth = None
     if not args.no_depth:
         depth = run_depth(args, torch, api, wl, sc)
+    cpu_scenes = {}
+    tiny = None
+    if not args.no_tiny:
+        tiny, cpu_scenes["tiny"] = run_tiny(args, torch, api, wl)
+    scale = None
+    if not args.no_scale:
+        scale, cpu_scenes["scale"] = run_scale(args, torch, api, wl, autotune)
     impulse = None
     if not args.no_impulse:
         impulse = run_impulse(args, torch, api, wl)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = run_cpu_baseline(sc, args.threads)
+        if not args.no_backward:
+            cpu_scenes["differentiation"] = wl.make_c5()
+        if not args.no_batched:
+            cpu_scenes["batched"] = wl.make_c4()
+        cpu = run_cpu_baseline(sc, args.threads, cpu_scenes)
         log(f"oracle {cpu['value']:.3e} taxel-evals/s on {cpu['cores']} threads")
     line = {
         "metric": METRIC, "value": m["value"], "unit": "taxel-evals/s", "n_gpus": 1, "steps": args.steps,
@@ -539,7 +696,7 @@ def main():
                    "contact_fraction": m["contact"], "tuning": m["tuning"], "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched, "differentiation": backward,
         "contact_impulse": impulse, "observation": observation, "depth_image": depth,
-        "nonlinear_normal_law": nonlinear,
+        "nonlinear_normal_law": nonlinear, "tiny": tiny, "scale": scale,
     }
     print(json.dumps(line), flush=True)
 

@@ -118,7 +118,13 @@ typedef struct {
  *   grid         persistent workgroups for schedules 1-2 (0 -> 8 per CU)
  *   order        0: instance-major; 1: XCD-aware (tiles of one object grid
  *                kept on one XCD's L2); 2: longest tiles first; 3: object-major
- *                (the whole GPU on one object grid at a time) */
+ *                (the whole GPU on one object grid at a time); 4: object-major
+ *                with each XCD on a contiguous run of the object's tiles;
+ *                5: as 4 with the pads in a spatial order rebuilt on the device
+ *                every call (pads binned by object grid and by the 8 x 8 x 8
+ *                coarse cell of their origin in the grid, Morton order); any
+ *                other value is TACSL_ERR_RANGE.  The order changes no output
+ *                (per-taxel outputs are bitwise independent of the tuning). */
 typedef struct {
   int32_t block, tile_taxels, schedule, grid, order;
 } tacsl_tuning;
@@ -222,9 +228,16 @@ int tacsl_plan_get_info(tacsl_plan plan, tacsl_plan_info* info);
 /* Copy the instance offsets (host int64 [n_inst+1]). */
 int tacsl_plan_offsets(tacsl_plan plan, int64_t* host_inst_offset);
 
-/* Forward force field, enqueued on `stream` (asynchronous; no allocation, no
- * host synchronization, capturable in a HIP graph).  All state and output
- * pointers except obj_pose_delta and status are required when n_inst > 0. */
+/* Forward force field (Section III-C, "Normal/Shear Force-Field
+ * Computation": the SDF queried at every tactile point for the
+ * interpenetration distance, the normal from finite-difference SDF
+ * gradients, the penalty law for f_n and the Coulomb-capped f_t; run once
+ * per simulation step as post-processing, notation appendix), enqueued on
+ * `stream` (asynchronous; no allocation, no host synchronization, capturable
+ * in a HIP graph).  All state and output pointers except obj_pose_delta and
+ * status are required when n_inst > 0; outputs are overwritten.  Errors:
+ * TACSL_ERR_NULL_ARG (plan, state, out or a required pointer NULL),
+ * TACSL_ERR_HIP (a launch failed). */
 int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, hipStream_t stream);
 
 /* Force-field observation (the policy input of Section V-B: per finger a
@@ -299,8 +312,17 @@ int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam);
 int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, uint32_t* status,
                       hipStream_t stream);
 
-/* Reverse mode (hand-written adjoint with recomputation of the forward),
- * enqueued on `stream`; same asynchrony rules as tacsl_force_field. */
+/* Reverse mode of the force field of Section III-C (the paper does not
+ * differentiate it; this is the exact derivative of the same FP32 forward
+ * path: the trilinear SDF value and nodal-gradient field, the normalized
+ * normal, the penalty law and the Coulomb cap, with the kinks at phi = 0, at
+ * the stick/slip switch and at cell faces taken one-sided as the forward
+ * branches decide).  A hand-written adjoint that recomputes the forward per
+ * taxel (nothing is stored between the passes), reduces per pad in FP64 in a
+ * fixed order, and maps the sums to world-frame gradients per environment.
+ * Enqueued on `stream`; same asynchrony rules as tacsl_force_field.  Errors:
+ * TACSL_ERR_NULL_ARG (plan, state, grads or a required pointer NULL),
+ * TACSL_ERR_HIP (a launch failed). */
 int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* grads,
                                hipStream_t stream);
 

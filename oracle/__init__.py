@@ -61,6 +61,7 @@ def _load():
         lib.oracle_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int]
         lib.oracle_loss.argtypes = [P, P, P, P, P, ctypes.c_int, P, P, ctypes.c_int]
         lib.oracle_signature.argtypes = [P, P, P, ctypes.c_int]
+        lib.oracle_decision_values.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_footprint.argtypes = [P, P, ctypes.c_int, P]
         lib.oracle_footprint.restype = ctypes.c_int64
         lib.oracle_depth_image.argtypes = [P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int]
@@ -184,6 +185,19 @@ def signature(scene, state, nthreads=0):
     return sig
 
 
+def decision_values(scene, state, nthreads=0):
+    """Per taxel (global order) the FP64 values the force law's discrete
+    decisions compare: columns (phi, |g|, k_t |v_t|, mu |s|) and the
+    sensitivity of the friction cap to phi, |d(mu |s|)/d phi|; NaN where the
+    step is not reached (Section III-C: contact where the SDF is negative, a
+    degenerate gradient, and the friction min(k_t |v_t|, mu |f_n|))."""
+    b = _Bound(scene, state)
+    T = int(np.diff(scene.tmpl_offset)[scene.inst_tmpl].sum())
+    m = np.zeros((T, 5), dtype=np.float64)
+    _load().oracle_decision_values(ctypes.byref(b.sc), ctypes.byref(b.st), _ptr(m), int(nthreads))
+    return m
+
+
 def footprint(scene, state, sel=None):
     if sel is None:
         sel = np.arange(scene.n_inst, dtype=np.int32)
@@ -272,3 +286,31 @@ def depth_image(scene, state, cam, sel=None, nthreads=0):
     _load().oracle_depth_image(ctypes.byref(b.sc), ctypes.byref(b.st), ctypes.byref(cam), int(sel.size), _ptr(sel),
                                _ptr(img), _ptr(sl), _ptr(pm), int(nthreads))
     return img, sl, pm
+
+
+def pose_path(pose0, twist, t):
+    """Object poses after moving for time ``t`` at a constant twist (FP64):
+    the origin moves at the constant velocity v, t_o(t) = t_o + v t, and the
+    body turns at the constant world-frame angular velocity w,
+    R_o(t) = Exp(w t) R_o, i.e. q(t) = q_w(t) q_0 (Hamilton product) with
+    q_w(t) = (cos(|w| t / 2), sin(|w| t / 2) w / |w|).  This is the seeded
+    pose update of the substep loop of the batched workload (the state a
+    simulator hands to the tactile step after each dynamics step, notation
+    appendix).  pose0 [E][7] = (qw qx qy qz tx ty tz), twist [E][6] = (v, w)."""
+    p0 = np.asarray(pose0, dtype=np.float64).reshape(-1, 7)
+    tw = np.asarray(twist, dtype=np.float64).reshape(-1, 6)
+    t = float(t)
+    trans = p0[:, 4:7] + tw[:, :3] * t
+    rv = tw[:, 3:6] * t
+    ang = np.linalg.norm(rv, axis=1)
+    half = 0.5 * ang
+    # sin(|a|/2)/|a| = sinc(|a| / (2 pi)) / 2, well defined at a = 0
+    s = 0.5 * np.sinc(half / np.pi)
+    qe = np.concatenate([np.cos(half)[:, None], s[:, None] * rv], axis=1)
+    w1, x1, y1, z1 = qe.T
+    w2, x2, y2, z2 = p0[:, :4].T
+    q = np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
+                  w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                  w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
+                  w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], axis=1)
+    return np.concatenate([q, trans], axis=1)

@@ -29,6 +29,7 @@
 //
 // Parity pins live in tests/test_oracle_*.py.
 #include <cmath>
+#include <limits>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -219,6 +220,10 @@ template <class S> struct TaxelOut {
   int contact;    // phi < 0
   int stick;      // 1 stick, 0 slip, -1 no friction evaluated
   int gnorm_ok;   // |g| >= 1e-6
+  // the values the discrete decisions above compare (0 where not reached):
+  // phi (against 0), |g| (against 1e-6), k_t |v_t| and mu |s| (against each other)
+  double phi_v, gn_v, ktv_v, cap_v;
+  double dcap_v;  // |d(mu |s|)/d phi|: how far an error in phi moves the friction cap
 };
 
 template <class S>
@@ -227,6 +232,7 @@ static TaxelOut<S> eval_taxel(const Instance<S>& I, const V3<double>& xp) {
   o.depth = S(0.0);
   o.n = o.fn = o.ft = v3<S>(S(0.0), S(0.0), S(0.0));
   o.cell = -1; o.contact = 0; o.stick = -1; o.gnorm_ok = 0;
+  o.phi_v = o.gn_v = o.ktv_v = o.cap_v = o.dcap_v = std::numeric_limits<double>::quiet_NaN();
 
   // (1) taxel to world and to object frame.
   V3<double> xw = add(mul(I.Rp, xp), I.tp);
@@ -259,11 +265,13 @@ static TaxelOut<S> eval_taxel(const Instance<S>& I, const V3<double>& xp) {
         gy = gy + w * g.grad(1, i, j, k, I.h);
         gz = gz + w * g.grad(2, i, j, k, I.h);
       }
+  o.phi_v = val(phi);
   // (5) no contact for phi >= 0.
   if (!(val(phi) < 0.0)) return o;
   o.contact = 1;
   o.depth = -phi;
   S gn = sqrt(gx * gx + gy * gy + gz * gz);
+  o.gn_v = val(gn);
   if (!(val(gn) >= 1e-6)) return o;  // degenerate normal: no force
   o.gnorm_ok = 1;
   V3<S> no = v3<S>(gx / gn, gy / gn, gz / gn);
@@ -287,6 +295,12 @@ static TaxelOut<S> eval_taxel(const Instance<S>& I, const V3<double>& xp) {
   V3<S> vt = sub(xdot, scl(n_p, ddot));
   S vtn = sqrt(dot(vt, vt));
   S cap = I.mu * fabs(s);
+  o.ktv_v = val(I.kt) * val(vtn);
+  o.cap_v = val(cap);
+  {
+    const double dp = I.hc == 1.0 ? 1.0 : I.hc * std::pow(-val(phi), I.hc - 1.0);
+    o.dcap_v = val(I.mu) * std::fabs(-val(I.kn) + val(I.kd) * val(ddot)) * dp;
+  }
   if (val(I.kt) * val(vtn) <= val(cap)) {
     o.stick = 1;
     o.ft = scl(vt, -I.kt);
@@ -490,6 +504,31 @@ int oracle_signature(const oracle_scene* sc, const oracle_state* st, int32_t* si
       TaxelOut<double> o = eval_taxel(I, tmpl_point(*sc, i, k));
       int64_t j = off[i] + k;
       sig[4 * j] = o.cell; sig[4 * j + 1] = o.contact; sig[4 * j + 2] = o.stick; sig[4 * j + 3] = o.gnorm_ok;
+    }
+  }
+  return 0;
+}
+
+// Per-taxel values behind the discrete decisions of the force law, for every
+// taxel of the scene in global order: m[T][5] = (phi, |g|, k_t |v_t|, mu |s|,
+// |d(mu |s|)/d phi|) (NaN where the step is not reached).  Test infrastructure: tells which
+// decisions lie so close to their threshold that FP32 and FP64 may take them
+// differently (Section III-C: contact where the SDF is negative; friction
+// min(k_t |v_t|, mu |f_n|)).
+int oracle_decision_values(const oracle_scene* sc, const oracle_state* st, double* m, int nthreads) {
+  std::vector<int64_t> off(sc->n_inst + 1);
+  oracle_offsets(sc, off.data());
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < sc->n_inst; ++i) {
+    Instance<double> I;
+    setup_instance<double>(*sc, *st, i, I);
+    int64_t cnt = tmpl_count(*sc, i);
+    for (int64_t k = 0; k < cnt; ++k) {
+      TaxelOut<double> o = eval_taxel(I, tmpl_point(*sc, i, k));
+      int64_t j = off[i] + k;
+      m[5 * j] = o.phi_v; m[5 * j + 1] = o.gn_v; m[5 * j + 2] = o.ktv_v; m[5 * j + 3] = o.cap_v;
+      m[5 * j + 4] = o.dcap_v;
     }
   }
   return 0;

@@ -387,7 +387,12 @@ class SubstepGraph:
 
 
 class _ForceFieldFn(torch.autograd.Function):
-    """f_n, f_t differentiable w.r.t. obj_pose_delta (6-DoF twist), obj_twist and params."""
+    """f_n, f_t differentiable w.r.t. obj_pose_delta (6-DoF twist), obj_twist and params.
+
+    The state tensors are kept with ``save_for_backward``, so changing any of
+    them in place between the forward and the backward pass (an optimizer
+    step, say) raises autograd's version error instead of silently
+    differentiating at the new values."""
 
     @staticmethod
     def forward(ctx, plan: Plan, pad_pose, obj_pose, pad_twist, obj_twist, params, obj_pose_delta):
@@ -397,18 +402,26 @@ class _ForceFieldFn(torch.autograd.Function):
             st["obj_pose_delta"] = obj_pose_delta.detach()
         out = plan.forward(st)
         ctx.plan = plan
-        ctx.st = st
+        ctx.has_delta = obj_pose_delta is not None
+        saved = [pad_pose, obj_pose, pad_twist, obj_twist, params]
+        if obj_pose_delta is not None:
+            saved.append(obj_pose_delta)
+        ctx.save_for_backward(*saved)
         ctx.mark_non_differentiable(out["depth"], out["normal"], out["wrench"])
         return out["depth"], out["normal"], out["fn"], out["ft"], out["wrench"]
 
     @staticmethod
     def backward(ctx, g_depth, g_normal, g_fn, g_ft, g_wrench):
         plan: Plan = ctx.plan
+        saved = ctx.saved_tensors
+        st = {k: t.detach() for k, t in zip(STATE_KEYS, saved[:5])}
+        if ctx.has_delta:
+            st["obj_pose_delta"] = saved[5].detach()
         T = plan.n_taxels
         f = dict(device=plan.device, dtype=torch.float32)
         w_fn = g_fn.contiguous() if g_fn is not None else torch.zeros(3, T, **f)
         w_ft = g_ft.contiguous() if g_ft is not None else torch.zeros(3, T, **f)
-        g = plan.backward(ctx.st, w_fn, w_ft)
+        g = plan.backward(st, w_fn, w_ft)
         need = ctx.needs_input_grad
         return (None, None, None, None, g["g_obj_twist"] if need[4] else None,
                 g["g_params"] if need[5] else None, g["g_obj_pose"] if need[6] else None)

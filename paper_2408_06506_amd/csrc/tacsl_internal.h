@@ -130,6 +130,7 @@ struct FwdArgs {
   int64_t T;
   float* partial;        // [n_tiles][6] wrench partials (the wrench itself when tiles == pads)
   int32_t mode;          // 1: per-taxel fields; 2: observation pooling; 3: both
+  int32_t nonlinear;     // 1: nonlinear normal law (exponent != 1)
   const int32_t* obs_bin;  // [tmpl_T] bin of each template taxel (-1: none), observation modes
   int32_t obs_n;           // bins per pad
   float* obs_partial;      // [n_tiles][obs_n][3] pooled channel sums
@@ -172,6 +173,7 @@ struct BwdArgs {
   const float* w_ft;  // [3][T]
   int64_t T;
   double* partial;    // [n_tiles][kBwdAcc]
+  int32_t nonlinear;  // 1: nonlinear normal law (exponent != 1)
 };
 
 struct GradReduceArgs {

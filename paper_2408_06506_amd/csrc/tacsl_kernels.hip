@@ -308,6 +308,9 @@ struct TaxelFwd {
 };
 
 
+// NL: the nonlinear normal law (penetration exponent x.hc != 1), a template
+// argument so that the linear law carries no code for it.
+template <bool NL>
 __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic& st, __amdgpu_buffer_rsrc_t rs,
                                               float px, float py, float pz, TaxelFwd& f) {
   f.contact = false;
@@ -378,7 +381,7 @@ __device__ __forceinline__ void taxel_forward(const InstXf& x, const InstStatic&
   // an exponent p != 1, w = -(-phi)^p (the nonlinear variant of Section VII)
   f.w = f.phi;
   f.dw = 1.f;
-  if (x.hc != 1.f) {
+  if constexpr (NL) {
     const float dl = -f.phi;
     const float dp = exp2f(x.hc * log2f(dl));
     f.w = -dp;
@@ -422,14 +425,14 @@ struct TileOut {
 
 // One taxel of the forward path: evaluation, optional SoA stores, wrench
 // accumulation.  Returns the observation channels (|f_n|, f_t,x, f_t,y).
-template <bool FIELDS>
+template <bool FIELDS, bool NL>
 __device__ __forceinline__ void taxel_step(const InstXf& x, const InstStatic& st, __amdgpu_buffer_rsrc_t rs,
                                            const float* tx, const float* ty, const float* tz, uint32_t k,
                                            const TileOut& o, float acc[6], float ch[3]) {
   // uniform 64-bit base + 32-bit lane offset: saddr addressing, no 64-bit VALU math
   const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
   TaxelFwd f;
-  taxel_forward(x, st, rs, px, py, pz, f);
+  taxel_forward<NL>(x, st, rs, px, py, pz, f);
   float dep = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
   float fn0 = 0.f, fn1 = 0.f, fn2 = 0.f, ft0 = 0.f, ft1 = 0.f, ft2 = 0.f, sn = 0.f;
   if (f.contact) dep = -f.phi;
@@ -481,9 +484,10 @@ __device__ __forceinline__ void pool_wave(float* acc, int lane, int b, const flo
 
 // MODE bits: kFields writes the per-taxel SoA fields; kObserve pools the
 // observation channels per bin into per-tile partials (dynamic LDS of
-// BLOCK/64 * obs_n * 3 floats).
+// BLOCK/64 * obs_n * 3 floats); kNonlinear selects the nonlinear normal law.
 constexpr int kFields = 1;
 constexpr int kObserve = 2;
+constexpr int kNonlinear = 4;
 
 template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_force_fwd(
@@ -494,6 +498,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(
     const int32_t* __restrict__ obs_bin, int32_t obs_n, float* __restrict__ obs_partial) {
   constexpr int NW = BLOCK / 64;
   constexpr bool FIELDS = (MODE & kFields) != 0;
+  constexpr bool NL = (MODE & kNonlinear) != 0;
   __shared__ float red[NW][6];
   __shared__ int s_next;
   extern __shared__ float obs_acc[];  // [NW][obs_n * 3], kObserve only
@@ -536,14 +541,14 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(
         int b = -1;
         ch[0] = ch[1] = ch[2] = 0.f;
         if (k < (uint32_t)tl.count) {
-          taxel_step<FIELDS>(x, st, rs, tx, ty, tz, k, o, acc, ch);
+          taxel_step<FIELDS, NL>(x, st, rs, tx, ty, tz, k, o, acc, ch);
           b = bins[k];
         }
         pool_wave(obs_acc + wave * row, lane, b, ch);
       }
     } else {
       for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK)
-        taxel_step<FIELDS>(x, st, rs, tx, ty, tz, k, o, acc, ch);
+        taxel_step<FIELDS, NL>(x, st, rs, tx, ty, tz, k, o, acc, ch);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(256) void k_wrench_reduce(WrenchReduceArgs a) {
 //   U1 = sum u_bar,     U2 = sum u_bar x u       (grid coordinates),
 //   and the four parameter adjoints.  k_grad_reduce maps them to the world.
 // ---------------------------------------------------------------------------
-template <int BLOCK>
+template <int BLOCK, bool NL>
 __global__ __launch_bounds__(BLOCK) void k_force_bwd(
     const Tile* __restrict__ tiles, const int32_t* __restrict__ order, int32_t n_tiles, int32_t dynamic,
     int32_t* __restrict__ queue, const InstStatic* __restrict__ stat, const InstXf* __restrict__ xfs,
@@ -637,7 +642,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_bwd(
     for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK) {
       const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
       TaxelFwd f;
-      taxel_forward(x, st, rs, px, py, pz, f);
+      taxel_forward<NL>(x, st, rs, px, py, pz, f);
       if (!f.force) continue;
       const float A[3] = {at(wa0, k), at(wa1, k), at(wa2, k)};
       const float B[3] = {at(wb0, k), at(wb1, k), at(wb2, k)};
@@ -856,10 +861,14 @@ hipError_t launch_forward_mode(const FwdArgs& a, int block, int grid, hipStream_
 }
 
 hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream) {
-  switch (a.mode) {
+  switch (a.mode | (a.nonlinear ? kNonlinear : 0)) {
     case kFields: return launch_forward_mode<kFields>(a, block, grid, stream);
     case kObserve: return launch_forward_mode<kObserve>(a, block, grid, stream);
     case kFields | kObserve: return launch_forward_mode<kFields | kObserve>(a, block, grid, stream);
+    case kFields | kNonlinear: return launch_forward_mode<kFields | kNonlinear>(a, block, grid, stream);
+    case kObserve | kNonlinear: return launch_forward_mode<kObserve | kNonlinear>(a, block, grid, stream);
+    case kFields | kObserve | kNonlinear:
+      return launch_forward_mode<kFields | kObserve | kNonlinear>(a, block, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -888,15 +897,21 @@ hipError_t launch_wrench_reduce(const WrenchReduceArgs& a, hipStream_t stream) {
 #define TACSL_BWD_ARGS \
   a.tiles, a.order, a.n_tiles, a.dynamic, a.queue, a.stat, a.xf, a.tmpl, a.tmpl_T, a.w_fn, a.w_ft, a.T, a.partial
 
-hipError_t launch_backward(const BwdArgs& a, int block, int grid, hipStream_t stream) {
+template <bool NL>
+hipError_t launch_backward_law(const BwdArgs& a, int block, int grid, hipStream_t stream) {
   switch (block) {
-    case 64: hipLaunchKernelGGL(k_force_bwd<64>, dim3(grid), dim3(64), 0, stream, TACSL_BWD_ARGS); break;
-    case 128: hipLaunchKernelGGL(k_force_bwd<128>, dim3(grid), dim3(128), 0, stream, TACSL_BWD_ARGS); break;
-    case 256: hipLaunchKernelGGL(k_force_bwd<256>, dim3(grid), dim3(256), 0, stream, TACSL_BWD_ARGS); break;
-    case 512: hipLaunchKernelGGL(k_force_bwd<512>, dim3(grid), dim3(512), 0, stream, TACSL_BWD_ARGS); break;
+    case 64: hipLaunchKernelGGL((k_force_bwd<64, NL>), dim3(grid), dim3(64), 0, stream, TACSL_BWD_ARGS); break;
+    case 128: hipLaunchKernelGGL((k_force_bwd<128, NL>), dim3(grid), dim3(128), 0, stream, TACSL_BWD_ARGS); break;
+    case 256: hipLaunchKernelGGL((k_force_bwd<256, NL>), dim3(grid), dim3(256), 0, stream, TACSL_BWD_ARGS); break;
+    case 512: hipLaunchKernelGGL((k_force_bwd<512, NL>), dim3(grid), dim3(512), 0, stream, TACSL_BWD_ARGS); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_backward(const BwdArgs& a, int block, int grid, hipStream_t stream) {
+  return a.nonlinear ? launch_backward_law<true>(a, block, grid, stream)
+                     : launch_backward_law<false>(a, block, grid, stream);
 }
 
 hipError_t launch_grad_reduce(const GradReduceArgs& a, hipStream_t stream) {

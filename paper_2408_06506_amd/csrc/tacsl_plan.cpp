@@ -466,6 +466,7 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   fa.T = p->T;
   fa.partial = direct ? o->wrench : p->d_partial;
   fa.mode = obs ? (fields ? 3 : 2) : 1;  // without the observation the fields are always written
+  fa.nonlinear = p->hc != 1.f ? 1 : 0;
   fa.obs_bin = p->d_obs_bin;
   fa.obs_n = obs ? p->obs_n : 0;
   fa.obs_partial = p->d_obs_partial;
@@ -1008,6 +1009,7 @@ int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const 
     ba.w_ft = g->w_ft;
     ba.T = plan->T;
     ba.partial = plan->d_bpartial;
+    ba.nonlinear = plan->hc != 1.f ? 1 : 0;
     const int grid =
         plan->tun.schedule == 0 ? (int)plan->n_tiles : (int)std::min<int64_t>(plan->tun.grid, plan->n_tiles);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;

@@ -4,7 +4,12 @@ Tolerances (the force field's error budget in FP32 against FP64):
 * depth:  |d_gpu - d_ref| <= 1e-5 * max(|d_ref|, D), D = the workload's
   maximum penetration (1 mm for the tiny ball case, 2 mm otherwise);
   contact flags may therefore differ only within 1e-5 D of the surface;
-* forces: ||f_gpu - f_ref|| <= 1e-4 * max(||f_ref||, k_n D);
+* normal force: ||df_n|| <= max(1e-4 ||f_n||, k_n 1e-5 D): the depth floor
+  carried through f_n = s n, |ds/dphi| ~ k_n (measured worst 0.32 of it);
+* friction: ||df_t|| <= 1e-4 max(||f_t||, k_n D): a sticking taxel's
+  f_t = -k_t v_t moves by k_t |x_dot| |dn|, and the normal's own FP32 error
+  reaches ~3e-5 next to SDF features (k_t |x_dot| 3e-5 ~ 5e-4 N here), so
+  the floor stays at 1e-4 k_n D = 2e-3 N (measured worst 0.18 of it);
 * normals: ||n_gpu - n_ref|| <= 1e-4 where both are in contact and
   d_ref > 1e-5 D;
 * wrench (per pad): |dF| <= 1e-4 * sum ||f|| + n_c k_n 1e-5 D and
@@ -34,22 +39,30 @@ def rows_of(offsets, sel):
 
 
 def compare(scene, gpu, ref, D, kn, sel=None, what=""):
-    """Assert the GPU outputs (restricted to `sel` pads) match the oracle."""
+    """Assert the GPU outputs (restricted to `sel` pads) match the oracle.
+    Prints the worst error-to-bound ratio of each field and returns them."""
     sel = np.arange(scene.n_inst) if sel is None else np.asarray(sel)
     dg, dr = gpu["depth"], ref["depth"]
     err_d = np.abs(dg - dr)
     lim_d = 1e-5 * np.maximum(np.abs(dr), D)
     bad = err_d > lim_d
+    ratios = dict(depth=float(np.max(err_d / lim_d, initial=0.0)))
     assert not bad.any(), f"{what} depth: {bad.sum()} bad, worst {np.max(err_d / lim_d):.3g}x the bound"
     for k in ("fn", "ft"):
         e = np.linalg.norm(gpu[k] - ref[k], axis=0)
-        lim = 1e-4 * np.maximum(np.linalg.norm(ref[k], axis=0), kn * D)
+        fr = np.linalg.norm(ref[k], axis=0)
+        lim = np.maximum(1e-4 * fr, kn * 1e-5 * D) if k == "fn" else 1e-4 * np.maximum(fr, kn * D)
+        ratios[k] = float(np.max(e / lim, initial=0.0))
         bad = e > lim
         assert not bad.any(), f"{what} {k}: {bad.sum()} bad, worst {np.max(e / lim):.3g}x the bound"
     both = (dg > 0) & (dr > 1e-5 * D)
     en = np.linalg.norm(gpu["normal"][:, both] - ref["normal"][:, both], axis=0)
+    ratios["normal"] = float(en.max(initial=0.0) / 1e-4)
+    print(f"[parity] {what}: worst error / bound " + ", ".join(f"{k} {v:.3g}" for k, v in ratios.items()),
+          flush=True)
     assert np.all(en <= 1e-4), f"{what} normal: worst {en.max() if en.size else 0:.3g}"
     compare_wrench(scene, gpu["wrench"], ref, D, kn, sel=sel, gpu_depth=dg, what=what)
+    return ratios
 
 
 def compare_wrench(scene, wrench, ref, D, kn, sel=None, gpu_depth=None, extra_contacts=0, what=""):
@@ -80,19 +93,51 @@ def compare_wrench(scene, wrench, ref, D, kn, sel=None, gpu_depth=None, extra_co
         assert dT <= 1e-4 * sT + 1e-30, f"{what} wrench torque pad {i}: {dT} > 1e-4 * {sT}"
 
 
-def grad_blocks_close(g_gpu, g_ref, tol=1e-4, what="", g_abs=None):
+def near_decision_mask(scene, state64, D, rel=1e-4):
+    """Taxels whose discrete force-law decisions lie within the FP32 error of
+    their thresholds, where the FP32 path and the FP64 oracle may legitimately
+    decide differently and the gradient jumps (a kink of the loss): contact
+    (|phi| <= 1e-5 D, the depth floor), stick/slip
+    (|k_t |v_t| - mu |s|| <= rel (k_t |v_t| + mu |s|) + |d(mu |s|)/d phi| 1e-5 D:
+    the cap moves with the depth error the forward tolerance allows) and the degenerate
+    normal (| |g| - 1e-6 | <= rel 1e-6).  Returns a bool keep-mask [T]."""
+    m = oracle.decision_values(scene, state64)
+    phi, gn, ktv, cap, dcap = m[:, 0], m[:, 1], m[:, 2], m[:, 3], m[:, 4]
+    with np.errstate(invalid="ignore"):
+        near = np.abs(phi) <= 1e-5 * D
+        near |= np.abs(ktv - cap) <= rel * (ktv + cap) + dcap * 1e-5 * D
+        near |= np.abs(gn - 1e-6) <= rel * 1e-6
+    return ~near
+
+
+# Per-taxel relative error of the FP32 adjoint's gradient terms: measured at
+# most ~1e-6 of the sum of their magnitudes on every gradient test (random
+# weights, several scenes and launch shapes); the bound uses 10x that.
+ABS_TERM = 1e-5
+
+
+def grad_blocks_close(g_gpu, g_ref, tol=1e-4, what="", g_abs=None, abs_coef=ABS_TERM):
     """Per environment and block (pose, twist, params):
-    ||dg|| <= tol * max(||g_ref||, ||A||), where A (optional) is, per
-    component, the sum over taxels of |per-taxel contribution| -- the scale
-    of a sum that cancels, which per-taxel FP32 errors (e.g. 1e-5 relative on
-    a 0.1 mm depth) are relative to."""
+    ||dg|| <= tol ||g_ref|| + abs_coef ||A||, where A (optional) is, per
+    component, the sum over taxels of |per-taxel contribution| dL_k/dtheta.
+    Without A the bound is the plain relative one.  A loss with weights of
+    random sign cancels between taxels, and its gradient carries the rounding
+    of terms much larger than the sum: that part is bounded through A with
+    the per-taxel relative error.  Prints, per block, the worst error
+    relative to ||g_ref|| and to the bound; returns them as
+    {block: (rel, rel_to_bound)}."""
+    worst = {}
     for name, blk in (("pose", slice(0, 6)), ("twist", slice(6, 12)), ("params", slice(12, 16))):
         num = np.linalg.norm(g_gpu[:, blk] - g_ref[:, blk], axis=1)
-        den = np.linalg.norm(g_ref[:, blk], axis=1)
-        if g_abs is not None:
-            den = np.maximum(den, np.linalg.norm(g_abs[:, blk], axis=1))
-        ok = num <= tol * den + 1e-12
-        assert ok.all(), f"{what} {name}: worst {np.max(num / np.maximum(den, 1e-30)):.3g} (env {np.argmax(num / np.maximum(den, 1e-30))})"
+        nref = np.linalg.norm(g_ref[:, blk], axis=1)
+        bound = tol * nref + (0.0 if g_abs is None else abs_coef * np.linalg.norm(g_abs[:, blk], axis=1)) + 1e-12
+        rel = num / np.maximum(nref, 1e-30)
+        rel_b = num / bound
+        worst[name] = (float(rel.max(initial=0.0)), float(rel_b.max(initial=0.0)))
+        print(f"[grad] {what} {name}: worst |dg|/|g_ref| = {worst[name][0]:.3g}, "
+              f"worst error / bound = {worst[name][1]:.3g}", flush=True)
+        assert np.all(num <= bound), f"{what} {name}: worst {rel_b.max():.3g}x the bound (env {np.argmax(rel_b)})"
+    return worst
 
 
 def oracle_forward(scene, state64, sel=None, nthreads=0):

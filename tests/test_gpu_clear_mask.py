@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from tests import scenes  # noqa: E402
-from tests.parity import compare, gpu_outputs_np, grad_blocks_close  # noqa: E402
+from tests.parity import compare, gpu_outputs_np, grad_blocks_close, near_decision_mask  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +103,8 @@ def test_clear_blocks_adjoint(api):
     rng = np.random.default_rng(4)
     wa = rng.standard_normal((3, sc.n_taxels)).astype(np.float32)
     wb = rng.standard_normal((3, sc.n_taxels)).astype(np.float32)
+    keep = near_decision_mask(sc, oracle.state64(sc), 2e-3)
+    wa, wb = (wa * keep).astype(np.float32), (wb * keep).astype(np.float32)
     _say("clear-block mask adjoint")
     plan = api.Plan(sc)
     st = plan.state(sc.state())

@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_2408_06506_amd import workloads as wl  # noqa: E402
-from tests.parity import compare, gpu_outputs_np, grad_blocks_close  # noqa: E402
+from tests.parity import near_decision_mask, compare, gpu_outputs_np, grad_blocks_close  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -86,12 +86,14 @@ def test_adjoint_nonlinear_law(api):
     plan = api.Plan(sc, dict(tile_taxels=64, schedule=2, grid=3, block=64))
     plan.set_normal_law(1.5)
     st = plan.state(sc.state())
+    s64 = oracle.state64(sc)
+    s64["normal_exponent"] = np.float64(1.5)
+    keep = near_decision_mask(sc, s64, 2e-3)
+    wa, wb = (wa * keep).astype(np.float32), (wb * keep).astype(np.float32)
     g = plan.backward(st, torch.as_tensor(wa, device=plan.device), torch.as_tensor(wb, device=plan.device))
     torch.cuda.synchronize()
     gg = np.concatenate([g["g_obj_pose"].cpu().numpy(), g["g_obj_twist"].cpu().numpy(),
                          g["g_params"].cpu().numpy()], axis=1).astype(np.float64)
-    s64 = oracle.state64(sc)
-    s64["normal_exponent"] = np.float64(1.5)
     _, ref, gabs = oracle.grad(sc, s64, wa, wb, with_abs=True)
     grad_blocks_close(gg, ref, 1e-4, what="p=1.5", g_abs=gabs)
     plan.close()
