@@ -240,6 +240,24 @@ int tacsl_plan_offsets(tacsl_plan plan, int64_t* host_inst_offset);
  * TACSL_ERR_HIP (a launch failed). */
 int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, hipStream_t stream);
 
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * at call time (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same outputs as tacsl_force_field, bit for bit,
+ * but the buffers a call writes and reads back (per-pad prologue records,
+ * per-tile wrench partials, the dynamic-queue counter and, for order 5, the
+ * spatial-order tables) come from one static device array of the library,
+ * 16 MiB per GPU, held until the process ends, instead of the plan.  The call
+ * allocates and frees nothing.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (any plans, any streams) race; order them.
+ * The plan's device must be current.  Needs about
+ * 100 n_pads + 24 n_tiles bytes (+ 4 kB per object grid and 8 bytes per pad
+ * and per tile for order 5).  Errors: as tacsl_force_field, plus
+ * TACSL_ERR_UNSUPPORTED when the plan needs more scratch than that or its
+ * device index is 64 or above, and TACSL_ERR_STATE when the plan's device is
+ * not current. */
+int tacsl_force_field_noalloc(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out,
+                              hipStream_t stream);
+
 /* Force-field observation (the policy input of Section V-B: per finger a
  * small grid of bins with three channels).  For every pad and bin the
  * channels (|f_n|, f_t,x, f_t,y), pad frame, are averaged over the pad's

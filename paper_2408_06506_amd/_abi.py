@@ -31,7 +31,7 @@ EXPORTS = [
     "tacsl_force_field", "tacsl_force_field_backward", "tacsl_graph_create", "tacsl_graph_launch",
     "tacsl_graph_destroy", "tacsl_plan_timer_start", "tacsl_plan_timer_read", "tacsl_plan_destroy",
     "tacsl_contact_impulse", "tacsl_plan_set_observation", "tacsl_force_field_observe",
-    "tacsl_plan_set_camera", "tacsl_depth_image", "tacsl_plan_set_normal_law",
+    "tacsl_plan_set_camera", "tacsl_depth_image", "tacsl_plan_set_normal_law", "tacsl_force_field_noalloc",
 ]
 MAX_OBS_BINS = 256
 
@@ -105,6 +105,7 @@ def load():
     lib.tacsl_plan_get_info.argtypes = [P, P]
     lib.tacsl_plan_offsets.argtypes = [P, P]
     lib.tacsl_force_field.argtypes = [P, P, P, P]
+    lib.tacsl_force_field_noalloc.argtypes = [P, P, P, P]
     lib.tacsl_force_field_backward.argtypes = [P, P, P, P]
     lib.tacsl_graph_create.argtypes = [I32, P, I32, P, P, P]
     lib.tacsl_graph_launch.argtypes = [P, P]

@@ -221,6 +221,19 @@ class Plan:
                                                _stream_handle(stream)), "tacsl_force_field")
         return out
 
+    def forward_noalloc(self, st: Dict[str, torch.Tensor], out: Dict[str, torch.Tensor],
+                        stream=None) -> Dict[str, torch.Tensor]:
+        """Forward through tacsl_force_field_noalloc: the call's work buffers
+        come from the library's static device scratch (nothing is allocated;
+        calls on one GPU must not overlap).  ``out`` is required."""
+        self._check_state(st)
+        self._check_outputs(out)
+        s = self._state_struct(st)
+        o = self._out_struct(out)
+        _abi.check(self._lib.tacsl_force_field_noalloc(self._plan, ctypes.byref(s), ctypes.byref(o),
+                                                       _stream_handle(stream)), "tacsl_force_field_noalloc")
+        return out
+
     def set_observation(self, tmpl_bin, n_bins: int, scale=(1.0, 1.0, 1.0), clip: float = 0.0):
         """Install the observation epilogue: per pad and bin the mean of
         (|f_n|, f_t,x, f_t,y) over the bin's taxels, / scale, clipped to +-clip.

@@ -231,6 +231,14 @@ struct DepthArgs {
   uint32_t* status;        // may be null
 };
 
+// Static device scratch of the allocation-free forward entry point (bytes
+// per GPU) and the largest device index it serves.
+constexpr int64_t kScratchBytes = int64_t(16) << 20;
+constexpr int kMaxScratchDevices = 64;
+// Device address of the scratch array on `device`, which must be the current
+// device; resolved with hipGetSymbolAddress on the first call per device.
+hipError_t scratch_address(int device, void** out);
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t stream);
 hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream);
 hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* out, hipStream_t stream);
 hipError_t launch_block_slopes(const float* phi4, int nx, int ny, int nz, float4* raw, float4* out, hipStream_t stream);

@@ -30,6 +30,8 @@
 // fixed-order (deterministic, no float atomics).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tacsl.h"
 #include "tacsl_device.h"
 #include "tacsl_internal.h"
@@ -818,7 +820,46 @@ __global__ __launch_bounds__(64) void k_grad_reduce(GradReduceArgs a) {
   for (int c = 0; c < 4; ++c) a.g_params[4 * (int64_t)e + c] = (float)gk[c];
 }
 
+// Fill n 32-bit words with zero (a kernel, not a memset, so that it also
+// replays correctly inside captured graphs).
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Device scratch of the allocation-free forward entry point: one static
+// array per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address resolved below, once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 }  // namespace
+
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+hipError_t scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxScratchDevices] = {};
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
 
 hipError_t launch_prepare_grid(const float* phi, float4* out, int nx, int ny, int nz, float h, uint32_t* bad,
                                hipStream_t stream) {

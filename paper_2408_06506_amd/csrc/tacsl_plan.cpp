@@ -405,27 +405,86 @@ int install_worklist(tacsl_plan p, const tacsl_tuning& t) {
   return TACSL_OK;
 }
 
+// Buffers one forward call writes and reads back: the plan's own, or carved
+// from the library's static device scratch (tacsl_force_field_noalloc).
+struct CallBuffers {
+  InstXf* xf;
+  int32_t* queue;
+  float* partial;
+  int32_t* order;
+  uint32_t* sp_hist;
+  uint32_t* sp_cursor;
+  int32_t* sp_bin;
+  int32_t* sp_grp_tile;
+};
+
+CallBuffers plan_buffers(const tacsl_plan p) {
+  return CallBuffers{p->d_xf, p->d_queue, p->d_partial, p->d_order,
+                     p->d_sp_hist, p->d_sp_cursor, p->d_sp_bin, p->d_sp_grp_tile};
+}
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// Bytes of static scratch a forward call of plan p needs.
+int64_t scratch_bytes(const tacsl_plan p) {
+  int64_t b = align256(4) + align256((int64_t)p->n_inst * (int64_t)sizeof(InstXf)) +
+              align256(p->n_tiles * 6 * (int64_t)sizeof(float));
+  if (p->tun.order == 5) {
+    const int64_t nb = (int64_t)tacsl::kSpatialBins * std::max(p->n_sdf, 1);
+    b += 2 * align256(nb * 4) + align256((int64_t)p->n_inst * 4) + align256(((int64_t)p->n_sdf + 1) * 4) +
+         align256(p->n_tiles * 4);
+  }
+  return b;
+}
+
+// Carve the call buffers of plan p out of the scratch at `base` (order 5:
+// the spatial histogram is cleared by a kernel on `stream` first).
+int scratch_buffers(const tacsl_plan p, char* base, hipStream_t stream, CallBuffers* cb) {
+  *cb = plan_buffers(p);
+  char* q = base;
+  auto take = [&](int64_t bytes) {
+    char* r = q;
+    q += align256(bytes);
+    return r;
+  };
+  cb->queue = reinterpret_cast<int32_t*>(take(4));
+  cb->xf = reinterpret_cast<InstXf*>(take((int64_t)p->n_inst * (int64_t)sizeof(InstXf)));
+  cb->partial = reinterpret_cast<float*>(take(p->n_tiles * 6 * (int64_t)sizeof(float)));
+  if (p->tun.order == 5) {
+    const int64_t nb = (int64_t)tacsl::kSpatialBins * std::max(p->n_sdf, 1);
+    cb->sp_hist = reinterpret_cast<uint32_t*>(take(nb * 4));
+    cb->sp_cursor = reinterpret_cast<uint32_t*>(take(nb * 4));
+    cb->sp_bin = reinterpret_cast<int32_t*>(take((int64_t)p->n_inst * 4));
+    cb->sp_grp_tile = reinterpret_cast<int32_t*>(take(((int64_t)p->n_sdf + 1) * 4));
+    cb->order = reinterpret_cast<int32_t*>(take(p->n_tiles * 4));
+    if (tacsl::launch_zero_u32(cb->sp_hist, nb, stream) != hipSuccess) return TACSL_ERR_HIP;
+  }
+  return TACSL_OK;
+}
+
 // Spatial order (order 5): the prologue has binned the pads; rebuild the
 // slot -> tile map for this call.
-int enqueue_spatial(tacsl_plan p, hipStream_t stream) {
+int enqueue_spatial(tacsl_plan p, hipStream_t stream, const CallBuffers* cb = nullptr) {
   if (p->tun.order != 5) return TACSL_OK;
+  const CallBuffers b = cb ? *cb : plan_buffers(p);
   tacsl::SpatialArgs sa{};
   sa.n_inst = p->n_inst;
   sa.n_sdf = p->n_sdf;
   sa.n_tiles = (int32_t)p->n_tiles;
   sa.interleave = 1;
-  sa.hist = p->d_sp_hist;
-  sa.cursor = p->d_sp_cursor;
-  sa.bin = p->d_sp_bin;
-  sa.grp_tile_begin = p->d_sp_grp_tile;
+  sa.hist = b.sp_hist;
+  sa.cursor = b.sp_cursor;
+  sa.bin = b.sp_bin;
+  sa.grp_tile_begin = b.sp_grp_tile;
   sa.inst_tile_begin = p->d_inst_tile_begin;
-  sa.order = p->d_order;
+  sa.order = b.order;
   return tacsl::launch_spatial_order(sa, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
 }
 
 int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, hipStream_t stream,
-                    bool capturing, float* obs = nullptr) {
+                    bool capturing, float* obs = nullptr, const CallBuffers* bufs = nullptr) {
   if (p->n_inst == 0) return TACSL_OK;
+  const CallBuffers cb = bufs ? *bufs : plan_buffers(p);
   tacsl::PrologueArgs pa{};
   pa.pad_pose = s->pad_pose;
   pa.obj_pose = s->obj_pose;
@@ -434,29 +493,29 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   pa.params = s->params;
   pa.obj_pose_delta = s->obj_pose_delta;
   pa.stat = p->d_stat;
-  pa.xf = p->d_xf;
+  pa.xf = cb.xf;
   pa.n_inst = p->n_inst;
   pa.status = o->status;
-  pa.queue = p->d_queue;
+  pa.queue = cb.queue;
   pa.hc = p->hc;
   if (p->tun.order == 5) {
-    pa.sp_hist = p->d_sp_hist;
-    pa.sp_bin = p->d_sp_bin;
+    pa.sp_hist = cb.sp_hist;
+    pa.sp_bin = cb.sp_bin;
     pa.sp_inst_tile_begin = p->d_inst_tile_begin;
   }
   if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
-  int src = enqueue_spatial(p, stream);
+  int src = enqueue_spatial(p, stream, &cb);
   if (src != TACSL_OK) return src;
   const bool direct = p->n_tiles == p->n_inst;  // one tile per pad: tile id == pad id
   const bool fields = o->depth != nullptr;
   tacsl::FwdArgs fa{};
   fa.tiles = p->d_tiles;
-  fa.order = p->d_order;
+  fa.order = cb.order;
   fa.n_tiles = (int32_t)p->n_tiles;
   fa.dynamic = p->tun.schedule == 2 ? 1 : 0;
-  fa.queue = p->d_queue;
+  fa.queue = cb.queue;
   fa.stat = p->d_stat;
-  fa.xf = p->d_xf;
+  fa.xf = cb.xf;
   fa.tmpl = p->tmpl_xyz;
   fa.tmpl_T = p->tmpl_T;
   fa.depth = o->depth;
@@ -464,7 +523,7 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   fa.fn = o->fn;
   fa.ft = o->ft;
   fa.T = p->T;
-  fa.partial = direct ? o->wrench : p->d_partial;
+  fa.partial = direct ? o->wrench : cb.partial;
   fa.mode = obs ? (fields ? 3 : 2) : 1;  // without the observation the fields are always written
   fa.nonlinear = p->hc != 1.f ? 1 : 0;
   fa.obs_bin = p->d_obs_bin;
@@ -484,7 +543,7 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
     p->timer_n++;
   }
   if (!direct) {
-    tacsl::WrenchReduceArgs ra{p->d_inst_tile_begin, p->d_partial, o->wrench, p->n_inst};
+    tacsl::WrenchReduceArgs ra{p->d_inst_tile_begin, cb.partial, o->wrench, p->n_inst};
     if (tacsl::launch_wrench_reduce(ra, stream) != hipSuccess) return TACSL_ERR_HIP;
   }
   if (obs) {
@@ -731,6 +790,28 @@ int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_out
   rc = check_outputs(plan, out);
   if (rc != TACSL_OK) return rc;
   return enqueue_forward(plan, state, out, stream, false);
+}
+
+int tacsl_force_field_noalloc(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out,
+                              hipStream_t stream) {
+  if (!plan) return TACSL_ERR_NULL_ARG;
+  int rc = check_state(plan, state);
+  if (rc != TACSL_OK) return rc;
+  rc = check_outputs(plan, out);
+  if (rc != TACSL_OK) return rc;
+  if (plan->n_inst == 0) return TACSL_OK;
+  if (scratch_bytes(plan) > tacsl::kScratchBytes) return TACSL_ERR_UNSUPPORTED;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TACSL_ERR_HIP;
+  if (dev != plan->device) return TACSL_ERR_STATE;
+  void* base = nullptr;
+  const hipError_t e = tacsl::scratch_address(dev, &base);
+  if (e == hipErrorInvalidDevice) return TACSL_ERR_UNSUPPORTED;
+  if (e != hipSuccess || !base) return TACSL_ERR_HIP;
+  CallBuffers cb{};
+  rc = scratch_buffers(plan, static_cast<char*>(base), stream, &cb);
+  if (rc != TACSL_OK) return rc;
+  return enqueue_forward(plan, state, out, stream, false, nullptr, &cb);
 }
 
 int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* tmpl_bin, const float* scale,
