@@ -312,6 +312,15 @@ def run_batched_vs_plain(args, torch, api, wl, autotune):
     S = sc.obj_pose_steps.shape[0]
     log(f"c4 scene: {sc.n_env} envs, {sc.n_inst} pads, {sc.n_taxels} taxels/substep, {S} substeps "
         f"({time.time() - t0:.1f}s)")
+    dt = float(sc.meta["dt"])
+
+    def path_of(p, scene):
+        """The substep pose path of a plan: poses at s dt from the step-0 pose and
+        twist, written inside the graph before each substep's forward."""
+        st0 = p.state(scene.state(0))
+        return dict(pose0=st0["obj_pose"], twist=st0["obj_twist"], dt=dt,
+                    poses=torch.empty(S, scene.n_env, 7, device=p.device))
+
     # batched: one plan, persistent schedules only, autotuned
     plan = api.Plan(sc, dict(tile_taxels=2048, schedule=2, order=2))
     states = [plan.state(sc.state(s)) for s in range(S)]
@@ -322,21 +331,34 @@ def run_batched_vs_plain(args, torch, api, wl, autotune):
     out = plan.new_outputs()
     wrench = torch.empty(S, sc.n_inst, 6, device=plan.device)
     outs = [dict(out, wrench=wrench[s]) for s in range(S)]
-    g_b = api.SubstepGraph(plan, states, outs)
-    # plain: one default plan per (pad resolution, grid size) group, all
+    path_b = path_of(plan, sc)
+    g_b = api.SubstepGraph(plan, states, outs, paths=path_b)
+    # plain: one plan per (pad resolution, grid size) group, each autotuned
+    # over every schedule (a superset of the batched plan's search), all
     # groups launched in every substep (one graph, substep-major)
     groups = wl.c4_groups(sc)
     subs = [wl.subset_scene(sc, g) for g in groups]
-    plains, p_states, p_outs, pouts = [], [], [], []
-    for sub in subs:
+    plains, p_states, p_outs, pouts, p_paths, p_tun = [], [], [], [], [], []
+    for gi, sub in enumerate(subs):
         p = api.Plan(sub)
         po = p.new_outputs()
+        pst = [p.state(sub.state(s)) for s in range(S)]
+        if not args.no_tune:
+            r = autotune.autotune(p, sub, pst[0], po, reps=5, schedules=(0, 1, 2), tag=f"c4-plain-{gi}")
+            ms_g = r["ms"]
+        else:
+            ms_g = None
+        res_g = int(np.diff(sub.tmpl_offset)[sub.inst_tmpl[0]])
+        p_tun.append({"taxels_per_pad": res_g, "grid": int(sub.sdf_dims[0][0]), "envs": sub.n_env,
+                      "tuning": p.tuning, "tuned_ms": ms_g})
         pw = torch.empty(S, sub.n_inst, 6, device=p.device)
         plains.append(p)
-        p_states.append([p.state(sub.state(s)) for s in range(S)])
+        p_states.append(pst)
         p_outs.append([dict(po, wrench=pw[s]) for s in range(S)])
+        p_paths.append(path_of(p, sub))
         pouts.append((po, pw))
-    graphs_p = [api.SubstepGraph(plains, p_states, p_outs)]
+    log(f"plain groups tuned: {[t['tuning'] for t in p_tun]}")
+    graphs_p = [api.SubstepGraph(plains, p_states, p_outs, paths=p_paths)]
     torch.cuda.synchronize()
 
     def time_graphs(gs, reps):
@@ -373,11 +395,22 @@ def run_batched_vs_plain(args, torch, api, wl, autotune):
         fmag = (torch.linalg.vector_norm(po["fn"] + po["ft"], dim=0))
         scale = max(float(fmag.sum().item()) / max(sub.n_inst, 1), 1e-9)
         max_rel = max(max_rel, float((wb - pw).abs().max().item()) / scale)
+    # the poses the graphs stepped equal the closed form the workload records
+    # (object translating at its velocity; FP64 then FP32 on both sides)
+    host_poses = torch.as_tensor(sc.obj_pose_steps, device=plan.device)
+    poses_equal = bool(torch.equal(path_b["poses"], host_poses))
+    # roofline of one substep of the batched graph (pose step, prologue,
+    # per-taxel pass, wrench reduction), same byte count as the main leg
+    V = sdf_footprint_nodes("batched_uneven_4096_substep0", sc)
+    B = algorithmic_bytes(sc, V)
     res = {"speedup": ms_p / ms_b, "batched_ms_per_substep": ms_b / S, "plain_ms_per_substep": ms_p / S,
            "substeps": S, "taxel_evals_per_substep": sc.n_taxels, "plain_launch_groups": len(subs),
-           "batched_tuning": plan.tuning, "per_taxel_bitwise_equal": bitwise,
+           "batched_tuning": plan.tuning, "plain_group_tunings": p_tun, "per_taxel_bitwise_equal": bitwise,
            "wrench_max_rel_diff": max_rel, "tolerance": 1e-4,
-           "batched_taxel_evals_per_s": sc.n_taxels * S / (ms_b * 1e-3)}
+           "recorded_poses_equal_closed_form": poses_equal,
+           "batched_taxel_evals_per_s": sc.n_taxels * S / (ms_b * 1e-3),
+           "algorithmic_bytes_per_substep": B, "sdf_footprint_nodes_substep0": V,
+           "batched_frac_of_hbm_peak": B / (ms_b / S * 1e-3) / HBM_PEAK}
     for g in graphs_p:
         g.close()
     g_b.close()
@@ -407,7 +440,9 @@ def run_backward(args, torch, api, wl):
     best, best_ms = None, float("inf")
     for tun in (dict(), dict(block=256, tile_taxels=0, schedule=0, order=3),
                 dict(block=256, tile_taxels=0, schedule=0, order=5), dict(block=256, tile_taxels=512, schedule=0, order=5),
-                dict(block=512, tile_taxels=0, schedule=0, order=5), dict(block=128, tile_taxels=0, schedule=0, order=5)):
+                dict(block=512, tile_taxels=0, schedule=0, order=5), dict(block=128, tile_taxels=0, schedule=0, order=5),
+                dict(block=256, tile_taxels=0, schedule=2, grid=1024, order=5),
+                dict(block=128, tile_taxels=256, schedule=0, order=5)):
         plan.set_tuning(tun)
         for _ in range(2):
             plan.backward(st, wa_t, wb_t, g)

@@ -353,6 +353,40 @@ int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const 
 int tacsl_graph_create(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_state* states,
                        const tacsl_outputs* outs, tacsl_graph* out);
 
+/* Closed-form object poses along a constant twist (the seeded per-substep
+ * pose update of a substep loop; the paper's tactile step reads the state the
+ * dynamics step left, notation appendix): for every environment e,
+ *   t_o(t) = t_o + v t,   R_o(t) = Exp(w t) R_o   (w the world-frame angular
+ *   velocity), i.e. q(t) = (cos(|w| t/2), sin(|w| t/2) w/|w|) * q_0,
+ * computed in FP64 and stored as FP32.
+ *   pose0  device float [n_env][7] (qw qx qy qz tx ty tz), twist device float
+ *          [n_env][6] (v, w), pose device float [n_env][7] out (may not
+ *          alias pose0); t the elapsed time (finite).
+ * Errors: TACSL_ERR_SHAPE (n_env < 0), TACSL_ERR_NULL_ARG, TACSL_ERR_RANGE (t
+ * not finite), TACSL_ERR_HIP.  Asynchronous on `stream`, no allocation,
+ * capturable. */
+int tacsl_pose_step(int32_t n_env, const float* pose0, const float* twist, double t, float* pose,
+                    hipStream_t stream);
+
+/* A plan's substep pose path for tacsl_graph_create_path: before substep s
+ * the graph writes the object poses at time s dt from (pose0, twist) into row
+ * s of poses (device float [n_steps][n_env][7], the recorded path), and the
+ * plan's forward of that substep reads them (the state's obj_pose is then
+ * ignored).  poses = NULL: no path for this plan. */
+typedef struct {
+  const float* pose0;
+  const float* twist;
+  double dt;
+  float* poses;
+} tacsl_pose_path;
+
+/* As tacsl_graph_create, with a pose path per plan (paths may be NULL, or
+ * hold a NULL poses entry for plans without one): each captured substep runs
+ * the path's pose step, then the forward (prologue, per-taxel pass, wrench
+ * reduction) on those poses. */
+int tacsl_graph_create_path(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_pose_path* paths,
+                            const tacsl_state* states, const tacsl_outputs* outs, tacsl_graph* out);
+
 /* Replay the captured steps on `stream`. */
 int tacsl_graph_launch(tacsl_graph graph, hipStream_t stream);
 

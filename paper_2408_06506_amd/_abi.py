@@ -32,6 +32,7 @@ EXPORTS = [
     "tacsl_graph_destroy", "tacsl_plan_timer_start", "tacsl_plan_timer_read", "tacsl_plan_destroy",
     "tacsl_contact_impulse", "tacsl_plan_set_observation", "tacsl_force_field_observe",
     "tacsl_plan_set_camera", "tacsl_depth_image", "tacsl_plan_set_normal_law", "tacsl_force_field_noalloc",
+    "tacsl_pose_step", "tacsl_graph_create_path",
 ]
 MAX_OBS_BINS = 256
 
@@ -48,6 +49,10 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class PosePath(ctypes.Structure):
+    _fields_ = [("pose0", P), ("twist", P), ("dt", ctypes.c_double), ("poses", P)]
 
 
 class State(ctypes.Structure):
@@ -108,6 +113,8 @@ def load():
     lib.tacsl_force_field_noalloc.argtypes = [P, P, P, P]
     lib.tacsl_force_field_backward.argtypes = [P, P, P, P]
     lib.tacsl_graph_create.argtypes = [I32, P, I32, P, P, P]
+    lib.tacsl_graph_create_path.argtypes = [I32, P, I32, P, P, P, P]
+    lib.tacsl_pose_step.argtypes = [I32, P, P, ctypes.c_double, P, P]
     lib.tacsl_graph_launch.argtypes = [P, P]
     lib.tacsl_graph_destroy.argtypes = [P]
     lib.tacsl_plan_timer_start.argtypes = [P, I32]

@@ -358,9 +358,10 @@ class SubstepGraph:
     substep 1, ...).
     """
 
-    def __init__(self, plans, states, outs):
+    def __init__(self, plans, states, outs, paths=None):
         if isinstance(plans, Plan):
             plans, states, outs = [plans], [states], [outs]
+            paths = None if paths is None else [paths]
         plans = list(plans)
         n_steps = len(states[0]) if states else 0
         if (not plans or len(states) != len(plans) or len(outs) != len(plans) or n_steps == 0
@@ -371,7 +372,25 @@ class SubstepGraph:
                 p._check_state(st)
                 p._check_outputs(out)
         self.plans = plans
-        self._keep = (states, outs)
+        self._keep = (states, outs, paths)
+        parr_paths = None
+        if paths is not None:
+            if len(paths) != len(plans):
+                raise ValueError("need one pose path (or None) per plan")
+            items = []
+            for p, path in zip(plans, paths):
+                if path is None:
+                    items.append(_abi.PosePath(None, None, 0.0, None))
+                    continue
+                pose0, twist, dt, poses = path["pose0"], path["twist"], float(path["dt"]), path["poses"]
+                for name, t, shp in (("pose0", pose0, (p.n_env, 7)), ("twist", twist, (p.n_env, 6)),
+                                     ("poses", poses, (n_steps, p.n_env, 7))):
+                    if (t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != shp
+                            or t.device != p.device):
+                        raise ValueError(f"path[{name}] must be a contiguous float32 {shp} tensor on {p.device}")
+                items.append(_abi.PosePath(_ptr(pose0), _ptr(twist), dt, _ptr(poses)))
+            parr_paths = (_abi.PosePath * len(plans))(*items)
+        self._paths = parr_paths
         n = n_steps * len(plans)
         sarr = (_abi.State * n)(*[plans[p]._state_struct(states[p][s]) for s in range(n_steps)
                                   for p in range(len(plans))])
@@ -381,8 +400,8 @@ class SubstepGraph:
         self._g = ctypes.c_void_p(None)
         lib = plans[0]._lib
         torch.cuda.synchronize(plans[0].device)
-        _abi.check(lib.tacsl_graph_create(len(plans), parr, n_steps, sarr, oarr, ctypes.byref(self._g)),
-                   "tacsl_graph_create")
+        _abi.check(lib.tacsl_graph_create_path(len(plans), parr, n_steps, parr_paths, sarr, oarr,
+                                               ctypes.byref(self._g)), "tacsl_graph_create_path")
         for p in plans:
             p._graphs.append(self)
 
@@ -438,6 +457,23 @@ class _ForceFieldFn(torch.autograd.Function):
         need = ctx.needs_input_grad
         return (None, None, None, None, g["g_obj_twist"] if need[4] else None,
                 g["g_params"] if need[5] else None, g["g_obj_pose"] if need[6] else None)
+
+
+def pose_step(pose0: torch.Tensor, twist: torch.Tensor, t: float, out: Optional[torch.Tensor] = None,
+              stream=None) -> torch.Tensor:
+    """Object poses after time t at a constant twist (tacsl_pose_step):
+    origin t_o + v t, orientation Exp(w t) R_o.  pose0 float32 [E, 7],
+    twist float32 [E, 6] on one device; returns float32 [E, 7]."""
+    lib = _abi.load()
+    n = int(pose0.shape[0])
+    for name, t_, shp in (("pose0", pose0, (n, 7)), ("twist", twist, (n, 6))):
+        if t_.dtype != torch.float32 or not t_.is_contiguous() or tuple(t_.shape) != shp or t_.device != pose0.device:
+            raise ValueError(f"{name} must be a contiguous float32 {shp} tensor")
+    if out is None:
+        out = torch.empty(n, 7, device=pose0.device, dtype=torch.float32)
+    _abi.check(lib.tacsl_pose_step(n, _ptr(pose0), _ptr(twist), float(t), _ptr(out), _stream_handle(stream)),
+               "tacsl_pose_step")
+    return out
 
 
 def force_field(plan: Plan, pad_pose, obj_pose, pad_twist, obj_twist, params, obj_pose_delta=None):

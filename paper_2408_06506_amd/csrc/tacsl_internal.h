@@ -239,6 +239,8 @@ constexpr int kMaxScratchDevices = 64;
 // device; resolved with hipGetSymbolAddress on the first call per device.
 hipError_t scratch_address(int device, void** out);
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t stream);
+hipError_t launch_pose_step(const float* pose0, const float* twist, double t, int32_t n_env, float* pose,
+                            hipStream_t stream);
 hipError_t launch_spatial_order(const SpatialArgs& a, hipStream_t stream);
 hipError_t launch_phi_quad(const float4* grid, int nx, int ny, int nz, float* out, hipStream_t stream);
 hipError_t launch_block_slopes(const float* phi4, int nx, int ny, int nz, float4* raw, float4* out, hipStream_t stream);

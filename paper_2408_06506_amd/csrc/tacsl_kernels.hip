@@ -833,7 +833,39 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ p, int6
 // symbol); it uses the device address resolved below, once per device.
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
+// Object poses after moving for time t at a constant twist (FP64): origin at
+// t_o + v t, orientation Exp(w t) R_o (w the world-frame angular velocity),
+// i.e. q(t) = q_w(t) q_0 with q_w = (cos(|w| t / 2), sin(|w| t / 2) w / |w|).
+__global__ __launch_bounds__(256) void k_pose_step(const float* __restrict__ pose0, const float* __restrict__ twist,
+                                                   double t, int32_t n_env, float* __restrict__ pose) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_env) return;
+  const float* p = pose0 + 7 * (int64_t)e;
+  const float* w = twist + 6 * (int64_t)e;
+  float* o = pose + 7 * (int64_t)e;
+  for (int a = 0; a < 3; ++a) o[4 + a] = (float)((double)p[4 + a] + (double)w[a] * t);
+  const double rx = (double)w[3] * t, ry = (double)w[4] * t, rz = (double)w[5] * t;
+  const double ang = sqrt(rx * rx + ry * ry + rz * rz);
+  const double half = 0.5 * ang;
+  // sin(|a| / 2) / |a|, by its series below 1e-4 (error < 1e-18)
+  const double s = ang < 1e-4 ? 0.5 - ang * ang / 48.0 : sin(half) / ang;
+  const double w1 = cos(half), x1 = s * rx, y1 = s * ry, z1 = s * rz;
+  const double w2 = p[0], x2 = p[1], y2 = p[2], z2 = p[3];
+  o[0] = (float)(w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2);
+  o[1] = (float)(w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2);
+  o[2] = (float)(w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2);
+  o[3] = (float)(w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2);
+}
+
 }  // namespace
+
+hipError_t launch_pose_step(const float* pose0, const float* twist, double t, int32_t n_env, float* pose,
+                            hipStream_t stream) {
+  if (n_env <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pose_step, dim3((unsigned)((n_env + 255) / 256)), dim3(256), 0, stream, pose0, twist, t, n_env,
+                     pose);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;

@@ -1121,21 +1121,45 @@ int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const 
   return TACSL_OK;
 }
 
+int tacsl_pose_step(int32_t n_env, const float* pose0, const float* twist, double t, float* pose,
+                    hipStream_t stream) {
+  if (n_env < 0) return TACSL_ERR_SHAPE;
+  if (n_env == 0) return TACSL_OK;
+  if (!pose0 || !twist || !pose) return TACSL_ERR_NULL_ARG;
+  if (!std::isfinite(t)) return TACSL_ERR_RANGE;
+  return tacsl::launch_pose_step(pose0, twist, t, n_env, pose, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
+}
+
 int tacsl_graph_create(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_state* states,
                        const tacsl_outputs* outs, tacsl_graph* out) {
+  return tacsl_graph_create_path(n_plans, plans, n_steps, nullptr, states, outs, out);
+}
+
+int tacsl_graph_create_path(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_pose_path* paths,
+                            const tacsl_state* states, const tacsl_outputs* outs, tacsl_graph* out) {
   if (!out) return TACSL_ERR_NULL_ARG;
   *out = nullptr;
   if (!plans || !states || !outs) return TACSL_ERR_NULL_ARG;
+  if (paths)
+    for (int p = 0; p < n_plans; ++p)
+      if (paths[p].poses && (!paths[p].pose0 || !paths[p].twist || !std::isfinite(paths[p].dt)))
+        return paths[p].pose0 && paths[p].twist ? TACSL_ERR_RANGE : TACSL_ERR_NULL_ARG;
   if (n_plans < 1 || n_steps < 1) return TACSL_ERR_SHAPE;
   for (int p = 0; p < n_plans; ++p) {
     if (!plans[p]) return TACSL_ERR_NULL_ARG;
     for (int q = 0; q < p; ++q)
       if (plans[q] == plans[p]) return TACSL_ERR_STATE;
   }
+  // a plan with a pose path reads each substep's object pose from the row the
+  // path step writes
+  std::vector<tacsl_state> st(states, states + (int64_t)n_steps * n_plans);
+  for (int s = 0; s < n_steps; ++s)
+    for (int p = 0; p < n_plans; ++p)
+      if (paths && paths[p].poses) st[(int64_t)s * n_plans + p].obj_pose = paths[p].poses + (int64_t)s * 7 * plans[p]->n_env;
   for (int s = 0; s < n_steps; ++s)
     for (int p = 0; p < n_plans; ++p) {
       const int64_t k = (int64_t)s * n_plans + p;
-      int rc = check_state(plans[p], states + k);
+      int rc = check_state(plans[p], st.data() + k);
       if (rc != TACSL_OK) return rc;
       rc = check_outputs(plans[p], outs + k);
       if (rc != TACSL_OK) return rc;
@@ -1152,7 +1176,11 @@ int tacsl_graph_create(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps
   for (int s = 0; s < n_steps && rc == TACSL_OK; ++s)
     for (int p = 0; p < n_plans && rc == TACSL_OK; ++p) {
       const int64_t k = (int64_t)s * n_plans + p;
-      rc = enqueue_forward(plans[p], states + k, outs + k, cs, true);
+      if (paths && paths[p].poses && plans[p]->n_env > 0 &&
+          tacsl::launch_pose_step(paths[p].pose0, paths[p].twist, s * paths[p].dt, plans[p]->n_env,
+                                  paths[p].poses + (int64_t)s * 7 * plans[p]->n_env, cs) != hipSuccess)
+        rc = TACSL_ERR_HIP;
+      if (rc == TACSL_OK) rc = enqueue_forward(plans[p], st.data() + k, outs + k, cs, true);
     }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);

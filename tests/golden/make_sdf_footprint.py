@@ -23,6 +23,8 @@ WORKLOADS = {
     "roofline_8192x2x80x100_256": wl.make_c3,
     "differentiation_1024x2x40x50_128": wl.make_c5,
     "scale_1024x2x40x50_128": wl.make_c2,
+    "batched_uneven_4096_substep0": wl.make_c4,
+    "tiny_1x20x25_64_step0": wl.make_c1,
 }
 
 

@@ -26,7 +26,7 @@ def _header_functions():
 def test_library_exports_every_declared_symbol():
     lib = _abi.load()
     names = _header_functions()
-    assert len(names) == 23
+    assert len(names) == 25
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(_abi.EXPORTS) == names
@@ -219,3 +219,12 @@ def test_contact_impulse_host_validation():
     assert f(*args(10, lam=None)) == -1
     assert f(*args(10, kc=None)) == -1
     assert f(*args(10, kc=ctypes.c_void_p(4100))) == -3   # (kappa, c) rows must be 8-byte aligned
+
+
+def test_pose_step_host_validation():
+    """tacsl_pose_step rejects bad arguments before any launch (no GPU needed)."""
+    lib = _abi.load()
+    assert lib.tacsl_pose_step(-1, 1, 1, 0.0, 1, None) == -2
+    assert lib.tacsl_pose_step(3, None, 1, 0.0, 1, None) == -1
+    assert lib.tacsl_pose_step(3, 1, 1, float("inf"), 1, None) == -3
+    assert lib.tacsl_pose_step(0, None, None, 0.0, None, None) == 0

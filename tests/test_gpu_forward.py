@@ -246,8 +246,10 @@ def test_rejected_tuning_keeps_the_plan_usable(api):
 def test_batched_uneven_full_size(api):
     """4096 envs, 8192 pads of three resolutions on 24 grids (64/128/256^3),
     100 substeps in one HIP graph with the kind of launch the benchmark
-    times (persistent dynamic queue): per-taxel outputs of substeps 0, 1, 49
-    and 99 and the wrenches of all 100 substeps on 64 sampled pads."""
+    times (persistent dynamic queue), each substep stepping the object poses
+    in the graph before its forward: recorded poses equal to the workload's,
+    per-taxel outputs of substeps 0, 1, 49 and 99 and the wrenches of all 100
+    substeps on 64 sampled pads."""
     from tests.parity import compare_wrench
     sc = wl.make_c4()
     S = sc.obj_pose_steps.shape[0]
@@ -256,10 +258,16 @@ def test_batched_uneven_full_size(api):
     states = [plan.state(sc.state(s)) for s in range(S)]
     out = plan.new_outputs()
     wrench = torch.empty(S, sc.n_inst, 6, device=plan.device)
-    graph = api.SubstepGraph(plan, states, [dict(out, wrench=wrench[s]) for s in range(S)])
+    # the graph steps the object poses itself (closed form from the substep-0
+    # pose and twist) before each substep's forward
+    poses = torch.empty(S, sc.n_env, 7, device=plan.device)
+    path = dict(pose0=states[0]["obj_pose"], twist=states[0]["obj_twist"], dt=float(sc.meta["dt"]), poses=poses)
+    graph = api.SubstepGraph(plan, states, [dict(out, wrench=wrench[s]) for s in range(S)], paths=path)
     _say("c4 graph launch")
     graph.launch()
     torch.cuda.synchronize()
+    # recorded poses = the workload's closed-form substep poses, bit for bit
+    assert np.array_equal(poses.cpu().numpy(), sc.obj_pose_steps)
     sel = np.sort(np.random.default_rng(21).choice(sc.n_inst, 64, replace=False)).astype(np.int32)
     off = plan.offsets()
     assert off.tolist() == oracle.offsets(sc).tolist()
