@@ -583,6 +583,31 @@ def run_depth(args, torch, api, wl, sc):
     return res
 
 
+def run_copy(torch, mib=1024, reps=10):
+    """Bandwidth of a plain device-to-device copy of `mib` MiB (the runtime's
+    copy kernel), warm buffers, each copy bracketed by its own events: the
+    reference for what the HBM sustains with equal reads and writes."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.ones_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        dst.copy_(src)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    del src, dst
+    torch.cuda.empty_cache()
+    moved = 2 * n * 4
+    log(f"copy {mib} MiB: {ms:.4f} ms, {moved / (ms * 1e-3) / 1e12:.2f} TB/s read + write")
+    return {"bytes_moved_per_copy": moved, "ms_per_copy": ms, "TBps": moved / (ms * 1e-3) / 1e12,
+            "frac_of_hbm_peak": moved / (ms * 1e-3) / HBM_PEAK}
+
+
 def run_impulse(args, torch, api, wl):
     """Batched implicit soft-contact impulse: per call 16 B read (eps, eps_dot,
     1/m, env) and 8 B written (lambda, dv) per contact, plus 8 B per
@@ -643,6 +668,7 @@ def main():
     ap.add_argument("--only-main", action="store_true", help="roofline workload only (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied by a plain device copy before the run (counter scale reference)")
+    ap.add_argument("--only-copy", action="store_true", help="the plain device copy bandwidth only")
     args = ap.parse_args()
     if args.only_main:
         args.no_batched = True
@@ -674,6 +700,10 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {n * 4} bytes read, {n * 4} bytes written")
         del src, dst
+    copy = run_copy(torch)
+    if args.only_copy:
+        print(json.dumps({"copy_bandwidth": copy}), flush=True)
+        return
     m = run_main(args, torch, api, wl, autotune)
     sc = m["scene"]
     traffic = measured_traffic(m["tuning"])
@@ -731,7 +761,7 @@ def main():
                    "contact_fraction": m["contact"], "tuning": m["tuning"], "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "batched_vs_plain": batched, "differentiation": backward,
         "contact_impulse": impulse, "observation": observation, "depth_image": depth,
-        "nonlinear_normal_law": nonlinear, "tiny": tiny, "scale": scale,
+        "nonlinear_normal_law": nonlinear, "tiny": tiny, "scale": scale, "copy_bandwidth": copy,
     }
     print(json.dumps(line), flush=True)
 
