@@ -643,11 +643,13 @@ __global__ __launch_bounds__(BLOCK) void k_force_bwd(
     for (int c = 0; c < kBwdAcc; ++c) acc[c] = 0.f;
     for (uint32_t k = threadIdx.x; k < (uint32_t)tl.count; k += BLOCK) {
       const float px = at(tx, k), py = at(ty, k), pz = at(tz, k);
+      // the loss weights are requested with the template point, so that their
+      // latency overlaps the forward recomputation instead of following it
+      const float A[3] = {at(wa0, k), at(wa1, k), at(wa2, k)};
+      const float B[3] = {at(wb0, k), at(wb1, k), at(wb2, k)};
       TaxelFwd f;
       taxel_forward<NL>(x, st, rs, px, py, pz, f);
       if (!f.force) continue;
-      const float A[3] = {at(wa0, k), at(wa1, k), at(wa2, k)};
-      const float B[3] = {at(wb0, k), at(wb1, k), at(wb2, k)};
       // f_n = s n
       float nb[3], vb[3], vtb[3];
       for (int c = 0; c < 3; ++c) nb[c] = f.s * A[c];
