@@ -250,8 +250,8 @@ int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_out
  * allocates and frees nothing.  Every call on a GPU shares that GPU's array:
  * calls that overlap on one GPU (any plans, any streams) race; order them.
  * The plan's device must be current.  Needs about
- * 100 n_pads + 24 n_tiles bytes (+ 4 kB per object grid and 8 bytes per pad
- * and per tile for order 5).  Errors: as tacsl_force_field, plus
+ * 100 n_pads + 24 n_tiles bytes (+ 4 kB per object grid, 4 bytes per pad and
+ * 4 per tile for order 5).  Errors: as tacsl_force_field, plus
  * TACSL_ERR_UNSUPPORTED when the plan needs more scratch than that or its
  * device index is 64 or above, and TACSL_ERR_STATE when the plan's device is
  * not current. */
