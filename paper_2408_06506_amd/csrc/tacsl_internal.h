@@ -74,7 +74,8 @@ struct InstXf {
 
 // One unit of work: taxels [k0, k0 + count) of pad `inst`.
 struct Tile {
-  int32_t inst, k0, count, pad_;
+  int32_t inst, k0, count;
+  int32_t env;  // environment of the pad
 };
 
 struct PrologueArgs {
@@ -113,6 +114,20 @@ struct SpatialArgs {
   int32_t* order;                  // [n_tiles] out: slot -> tile id
 };
 
+// State inputs of the per-pad record when the forward kernel computes it
+// itself (fused mode: no prologue launch; orders 0-4, static or persistent
+// schedules, per-taxel fields without the observation).
+struct FusedIn {
+  const float* pad_pose;
+  const float* obj_pose;
+  const float* pad_twist;
+  const float* obj_twist;
+  const float* params;
+  const float* obj_pose_delta;  // may be null
+  uint32_t* status;             // may be null
+  float hc;
+};
+
 struct FwdArgs {
   const Tile* tiles;
   const int32_t* order;  // execution slot -> tile id
@@ -134,6 +149,8 @@ struct FwdArgs {
   const int32_t* obs_bin;  // [tmpl_T] bin of each template taxel (-1: none), observation modes
   int32_t obs_n;           // bins per pad
   float* obs_partial;      // [n_tiles][obs_n][3] pooled channel sums
+  int32_t fused;           // 1: each tile's workgroup computes its pad's record from `fin` (mode 1 only)
+  FusedIn fin;
 };
 
 // Observation epilogue: per pad and bin, channels (|f_n|, f_t,x, f_t,y)

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void k_prepare_grid(const float* __restrict__ 
 //   V = R_p^T [(v_p - v_o) - w_o x (t_p - t_o)],  W = R_p^T (w_p - w_o).
 // ---------------------------------------------------------------------------
 __device__ bool quat_to_R(const float* q, double R[9], uint32_t& bits) {
+#pragma clang fp contract(off)
   double w = q[0], x = q[1], y = q[2], z = q[3];
   double n2 = w * w + x * x + y * y + z * z;
   if (!(n2 > 0.0)) {
@@ -116,6 +117,7 @@ __device__ bool quat_to_R(const float* q, double R[9], uint32_t& bits) {
 
 // Rotation matrix of the rotation vector p (Rodrigues; series for tiny angles).
 __device__ void rotvec_to_R(const double p[3], double R[9]) {
+#pragma clang fp contract(off)
   const double t2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   double a, b;
   if (t2 < 1e-12) {
@@ -143,6 +145,7 @@ __device__ bool all_finite(const float* p, int n) {
 // Object world pose after the optional perturbation (FP64).
 __device__ bool object_pose(const float* obj_pose, const float* delta, double Ro[9], double to[3],
                             uint32_t& bits) {
+#pragma clang fp contract(off)
   if (!quat_to_R(obj_pose, Ro, bits)) return false;
   for (int a = 0; a < 3; ++a) to[a] = obj_pose[4 + a];
   if (delta) {
@@ -157,26 +160,26 @@ __device__ bool object_pose(const float* obj_pose, const float* delta, double Ro
   return true;
 }
 
-__global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && a.queue) *a.queue = 0;
-  if (i >= a.n_inst) return;
-  const InstStatic st = a.stat[i];
-  const int e = st.env;
-  const float* pp = a.pad_pose + 7 * (int64_t)i;
-  const float* op = a.obj_pose + 7 * (int64_t)e;
-  const float* pt = a.pad_twist + 6 * (int64_t)i;
-  const float* ot = a.obj_twist + 6 * (int64_t)e;
-  const float* pr = a.params + 4 * (int64_t)e;
-  const float* dl = a.obj_pose_delta ? a.obj_pose_delta + 6 * (int64_t)e : nullptr;
-  uint32_t bits = 0;
+// The record of pad i (and the status bits its inputs raise).  No FP
+// contraction here or in the helpers above: the record has the same bits in
+// k_prologue and in the fused forward kernel, whatever the surrounding code.
+__device__ __forceinline__ void pad_record(const float* pad_pose, const float* obj_pose, const float* pad_twist,
+                                           const float* obj_twist, const float* params, const float* obj_pose_delta,
+                                           const InstStatic& st, int64_t i, int e, float hc, InstXf& x,
+                                           uint32_t& bits) {
+#pragma clang fp contract(off)
+  const float* pp = pad_pose + 7 * i;
+  const float* op = obj_pose + 7 * (int64_t)e;
+  const float* pt = pad_twist + 6 * i;
+  const float* ot = obj_twist + 6 * (int64_t)e;
+  const float* pr = params + 4 * (int64_t)e;
+  const float* dl = obj_pose_delta ? obj_pose_delta + 6 * (int64_t)e : nullptr;
   bool ok = all_finite(pp, 7) && all_finite(op, 7) && all_finite(pt, 6) && all_finite(ot, 6) &&
             all_finite(pr, 4) && (dl == nullptr || all_finite(dl, 6));
   if (!ok) bits |= 0x1u;
   double Rp[9], Ro[9], to[3];
   if (ok) ok = quat_to_R(pp, Rp, bits);
   if (ok) ok = object_pose(op, dl, Ro, to, bits);
-  InstXf x;
   if (ok) {
     const double tp[3] = {pp[4], pp[5], pp[6]};
     const double d[3] = {tp[0] - to[0], tp[1] - to[1], tp[2] - to[2]};
@@ -207,7 +210,18 @@ __global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
     for (int k = 0; k < 4; ++k) x.prm[k] = 0.f;
     x.ok = 0;
   }
-  x.hc = a.hc;
+  x.hc = hc;
+}
+
+__global__ __launch_bounds__(64) void k_prologue(PrologueArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && a.queue) *a.queue = 0;
+  if (i >= a.n_inst) return;
+  const InstStatic st = a.stat[i];
+  uint32_t bits = 0;
+  InstXf x;
+  pad_record(a.pad_pose, a.obj_pose, a.pad_twist, a.obj_twist, a.params, a.obj_pose_delta, st, i, st.env, a.hc, x,
+             bits);
   a.xf[i] = x;
   if (bits && a.status) atomicOr(a.status, bits);
   if (a.sp_hist) {
@@ -486,10 +500,23 @@ __device__ __forceinline__ void pool_wave(float* acc, int lane, int b, const flo
 
 // MODE bits: kFields writes the per-taxel SoA fields; kObserve pools the
 // observation channels per bin into per-tile partials (dynamic LDS of
-// BLOCK/64 * obs_n * 3 floats); kNonlinear selects the nonlinear normal law.
+// BLOCK/64 * obs_n * 3 floats); kNonlinear selects the nonlinear normal law;
+// kFused computes each tile's pad record in the kernel (wave 0, shared through
+// LDS) instead of reading the prologue's, so a call is one launch.
 constexpr int kFields = 1;
 constexpr int kObserve = 2;
 constexpr int kNonlinear = 4;
+constexpr int kFused = 8;
+
+// A record made uniform: every dword through the scalar unit.
+__device__ __forceinline__ InstXf uniform_record(const InstXf& v) {
+  InstXf u;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&v);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&u);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(InstXf) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+  return u;
+}
 
 template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_force_fwd(
@@ -497,12 +524,14 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(
     int32_t* __restrict__ queue, const InstStatic* __restrict__ stat, const InstXf* __restrict__ xfs,
     const float* __restrict__ tmpl, int64_t tmpl_T, float* __restrict__ depth, float* __restrict__ normal,
     float* __restrict__ fn, float* __restrict__ ft, int64_t T, float* __restrict__ partial,
-    const int32_t* __restrict__ obs_bin, int32_t obs_n, float* __restrict__ obs_partial) {
+    const int32_t* __restrict__ obs_bin, int32_t obs_n, float* __restrict__ obs_partial, const FusedIn fin) {
   constexpr int NW = BLOCK / 64;
   constexpr bool FIELDS = (MODE & kFields) != 0;
   constexpr bool NL = (MODE & kNonlinear) != 0;
+  constexpr bool FUSED = (MODE & kFused) != 0;
   __shared__ float red[NW][6];
   __shared__ int s_next;
+  __shared__ InstXf s_rec;  // kFused: the tile's pad record
   extern __shared__ float obs_acc[];  // [NW][obs_n * 3], kObserve only
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -511,7 +540,24 @@ __global__ __launch_bounds__(BLOCK) void k_force_fwd(
     const int tid = __builtin_amdgcn_readfirstlane(order[slot]);
     const Tile tl = tiles[tid];
     const InstStatic st = stat[tl.inst];
-    const InstXf x = xfs[tl.inst];
+    InstXf x;
+    if constexpr (FUSED) {
+      if (wave == 0) {
+        InstXf r;
+        uint32_t bits = 0;
+        // the environment comes with the tile, so the pose loads need not wait for the pad's static record
+        pad_record(fin.pad_pose, fin.obj_pose, fin.pad_twist, fin.obj_twist, fin.params, fin.obj_pose_delta, st,
+                   tl.inst, tl.env, fin.hc, r, bits);
+        if (lane == 0) {
+          s_rec = r;
+          if (bits && fin.status && tl.k0 == 0) atomicOr(fin.status, bits);  // once per pad
+        }
+      }
+      __syncthreads();
+      x = uniform_record(s_rec);
+    } else {
+      x = xfs[tl.inst];
+    }
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(st.grid, st.grid_bytes);
     const float* tx = tmpl + st.tmpl_off + tl.k0;
     const float* ty = tx + tmpl_T;
@@ -920,7 +966,7 @@ hipError_t launch_prologue(const PrologueArgs& a, hipStream_t stream) {
 
 #define TACSL_FWD_ARGS                                                                                  \
   a.tiles, a.order, a.n_tiles, a.dynamic, a.queue, a.stat, a.xf, a.tmpl, a.tmpl_T, a.depth, a.normal, a.fn, \
-      a.ft, a.T, a.partial, a.obs_bin, a.obs_n, a.obs_partial
+      a.ft, a.T, a.partial, a.obs_bin, a.obs_n, a.obs_partial, a.fin
 
 template <int MODE>
 hipError_t launch_forward_mode(const FwdArgs& a, int block, int grid, hipStream_t stream) {
@@ -936,8 +982,11 @@ hipError_t launch_forward_mode(const FwdArgs& a, int block, int grid, hipStream_
 }
 
 hipError_t launch_forward(const FwdArgs& a, int block, int grid, hipStream_t stream) {
-  switch (a.mode | (a.nonlinear ? kNonlinear : 0)) {
+  if (a.fused && (a.mode != kFields || a.dynamic)) return hipErrorInvalidValue;
+  switch (a.mode | (a.nonlinear ? kNonlinear : 0) | (a.fused ? kFused : 0)) {
     case kFields: return launch_forward_mode<kFields>(a, block, grid, stream);
+    case kFields | kFused: return launch_forward_mode<kFields | kFused>(a, block, grid, stream);
+    case kFields | kNonlinear | kFused: return launch_forward_mode<kFields | kNonlinear | kFused>(a, block, grid, stream);
     case kObserve: return launch_forward_mode<kObserve>(a, block, grid, stream);
     case kFields | kObserve: return launch_forward_mode<kFields | kObserve>(a, block, grid, stream);
     case kFields | kNonlinear: return launch_forward_mode<kFields | kNonlinear>(a, block, grid, stream);

@@ -96,12 +96,12 @@ int make_worklist(const tacsl_scene_desc& d, const tacsl_tuning& t, int xcd, std
     inst_tile_begin[i] = (int64_t)tiles.size();
     const int64_t cnt = tmpl_count(d, i);
     if (cnt == 0) {
-      tiles.push_back(Tile{i, 0, 0, 0});
+      tiles.push_back(Tile{i, 0, 0, d.inst_env[i]});
       continue;
     }
     const int64_t tsz = t.tile_taxels > 0 ? t.tile_taxels : cnt;
     for (int64_t k0 = 0; k0 < cnt; k0 += tsz)
-      tiles.push_back(Tile{i, (int32_t)k0, (int32_t)std::min(tsz, cnt - k0), 0});
+      tiles.push_back(Tile{i, (int32_t)k0, (int32_t)std::min(tsz, cnt - k0), d.inst_env[i]});
     if ((int64_t)tiles.size() > (int64_t)INT32_MAX) return TACSL_ERR_UNSUPPORTED;
   }
   inst_tile_begin[d.n_inst] = (int64_t)tiles.size();
@@ -481,10 +481,20 @@ int enqueue_spatial(tacsl_plan p, hipStream_t stream, const CallBuffers* cb = nu
   return tacsl::launch_spatial_order(sa, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
 }
 
+// Small launches (no more tiles than compute units) with orders 0-4 and a
+// static or persistent schedule: the forward kernel computes each tile's pad
+// record itself (its FP64 code raises the kernel to ~110 VGPRs, which only a
+// launch of at most one workgroup per CU does not feel), so a call is one
+// launch instead of two (plus the wrench reduction when pads span tiles).
+bool fused_forward(const tacsl_plan p, const float* obs) {
+  return obs == nullptr && p->tun.order != 5 && p->tun.schedule != 2 && p->n_tiles <= p->cu_count;
+}
+
 int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, hipStream_t stream,
                     bool capturing, float* obs = nullptr, const CallBuffers* bufs = nullptr) {
   if (p->n_inst == 0) return TACSL_OK;
   const CallBuffers cb = bufs ? *bufs : plan_buffers(p);
+  const bool fused = fused_forward(p, obs);
   tacsl::PrologueArgs pa{};
   pa.pad_pose = s->pad_pose;
   pa.obj_pose = s->obj_pose;
@@ -503,7 +513,7 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
     pa.sp_bin = cb.sp_bin;
     pa.sp_inst_tile_begin = p->d_inst_tile_begin;
   }
-  if (tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
+  if (!fused && tacsl::launch_prologue(pa, stream) != hipSuccess) return TACSL_ERR_HIP;
   int src = enqueue_spatial(p, stream, &cb);
   if (src != TACSL_OK) return src;
   const bool direct = p->n_tiles == p->n_inst;  // one tile per pad: tile id == pad id
@@ -529,6 +539,9 @@ int enqueue_forward(tacsl_plan p, const tacsl_state* s, const tacsl_outputs* o, 
   fa.obs_bin = p->d_obs_bin;
   fa.obs_n = obs ? p->obs_n : 0;
   fa.obs_partial = p->d_obs_partial;
+  fa.fused = fused ? 1 : 0;
+  fa.fin = tacsl::FusedIn{s->pad_pose, s->obj_pose, s->pad_twist, s->obj_twist, s->params, s->obj_pose_delta,
+                          o->status, p->hc};
   const int grid = p->tun.schedule == 0 ? (int)p->n_tiles : (int)std::min<int64_t>(p->tun.grid, p->n_tiles);
   bool timed = !capturing && p->timing();
   if (timed) {

@@ -290,3 +290,33 @@ def test_batched_uneven_full_size(api):
             assert np.array_equal(g["wrench"], ws[s])  # graph replay = eager launch
     graph.close()
     plan.close()
+
+
+def test_fused_record_matches_prologue(api):
+    """Launches of at most one workgroup per CU compute each pad's record in the
+    forward kernel instead of a prologue launch; the outputs, wrenches and
+    status bits are bitwise those of the prologue path."""
+    sc = wl.make_small(cfg_id=73, n_env=12)
+    res = {}
+    # tile 0: 24 tiles (fused); tile 64: 24 x 14 tiles, more than the CUs
+    # (prologue); order 5 always takes the prologue
+    for name, tun in (("fused", dict(tile_taxels=0, order=0)), ("prologue", dict(tile_taxels=64, order=0)),
+                      ("spatial", dict(tile_taxels=0, order=5))):
+        _say(f"fused vs prologue: {name} {tun}")
+        plan = api.Plan(sc, tun)
+        if name != "spatial":
+            assert (plan.info().n_tiles <= plan.info().cu_count) == (name == "fused")
+        st = plan.state(sc.state())
+        st["pad_pose"][5, 1] = float("inf")
+        out = plan.forward(st)
+        torch.cuda.synchronize()
+        res[name] = {k: v.clone() for k, v in out.items()}
+        plan.close()
+    for name in ("prologue", "spatial"):
+        for k in ("depth", "normal", "fn", "ft", "status"):
+            assert torch.equal(res["fused"][k], res[name][k]), (name, k)
+    # the same tiles (one per pad) sum the wrench in the same order; 64-taxel
+    # tiles sum per-tile partials, another FP32 order
+    assert torch.equal(res["fused"]["wrench"], res["spatial"]["wrench"])
+    torch.testing.assert_close(res["fused"]["wrench"], res["prologue"]["wrench"], rtol=1e-5, atol=1e-3)
+    assert int(res["fused"]["status"].item()) == 1
