@@ -160,16 +160,18 @@ def run_tiny(args, torch, api, wl):
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
+        h0 = time.perf_counter()
         for _ in range(reps):
             g.launch()
+        host_us = (time.perf_counter() - h0) * 1e6 / (reps * len(states))  # submission only
         b.record()
         torch.cuda.synchronize()
         us = a.elapsed_time(b) * 1e3 / (reps * len(states))
         g.close()
         if best is None or us < best[1]:
-            best = (tun, us)
+            best = (tun, us, host_us)
     plan.set_tuning(best[0])
-    us_graph = best[1]
+    us_graph, host_us = best[1], best[2]
     out = plan.new_outputs()
     for st in states[:10]:
         plan.forward(st, out)
@@ -187,7 +189,8 @@ def run_tiny(args, torch, api, wl):
     T = scenes[0].n_taxels
     res = {"workload": "tiny ball: 1 env x 1 pad 20x25 taxels, sphere r=10 mm at 64^3 / 0.5 mm, 100 seeded steps",
            "taxels_per_step": T, "tuning": tuning, "us_per_step_eager": wall * 1e6 / len(states),
-           "us_per_step_graph": us_graph, "kernel_avg_us": float(np.mean(kms)) * 1e3,
+           "us_per_step_graph": us_graph, "host_us_per_step_graph_submit": host_us,
+           "kernel_avg_us": float(np.mean(kms)) * 1e3,
            "taxel_evals_per_s_graph": T / (us_graph * 1e-6)}
     log(f"tiny: {res['us_per_step_eager']:.1f} us/step eager, {us_graph:.2f} us/step in a graph, "
         f"kernel {res['kernel_avg_us']:.2f} us")

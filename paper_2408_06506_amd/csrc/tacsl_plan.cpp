@@ -8,6 +8,8 @@
 #include <numeric>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "tacsl.h"
 #include "tacsl_internal.h"
 
@@ -16,6 +18,15 @@ using tacsl::InstXf;
 using tacsl::Tile;
 
 namespace {
+
+// Host-side range around each entry point that enqueues device work, named
+// after it; rocprofv3 --marker-trace shows them (a no-op with no tool attached).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 constexpr int64_t kMaxGridBytes = (int64_t(1) << 32) - 1;  // prepared grid addressed with 32-bit offsets
 constexpr int64_t kMaxPairStride = (int64_t(1) << 24) - 1;  // bytes per x-pair: a 24-bit multiplier operand
@@ -640,6 +651,7 @@ int tacsl_build_worklist(const tacsl_scene_desc* desc, const tacsl_tuning* tunin
 }
 
 int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, tacsl_plan* out) {
+  const Range range("tacsl_plan_create");
   if (!out) return TACSL_ERR_NULL_ARG;
   *out = nullptr;
   int rc = validate(desc);
@@ -767,6 +779,7 @@ int tacsl_plan_create(const tacsl_scene_desc* desc, const tacsl_tuning* tuning, 
 }
 
 int tacsl_plan_set_tuning(tacsl_plan plan, const tacsl_tuning* tuning) {
+  const Range range("tacsl_plan_set_tuning");
   if (!plan) return TACSL_ERR_NULL_ARG;
   if (plan->live_graphs > 0) return TACSL_ERR_STATE;
   tacsl_tuning t;
@@ -797,6 +810,7 @@ int tacsl_plan_offsets(tacsl_plan plan, int64_t* host_inst_offset) {
 }
 
 int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, hipStream_t stream) {
+  const Range range("tacsl_force_field");
   if (!plan) return TACSL_ERR_NULL_ARG;
   int rc = check_state(plan, state);
   if (rc != TACSL_OK) return rc;
@@ -807,6 +821,7 @@ int tacsl_force_field(tacsl_plan plan, const tacsl_state* state, const tacsl_out
 
 int tacsl_force_field_noalloc(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out,
                               hipStream_t stream) {
+  const Range range("tacsl_force_field_noalloc");
   if (!plan) return TACSL_ERR_NULL_ARG;
   int rc = check_state(plan, state);
   if (rc != TACSL_OK) return rc;
@@ -829,6 +844,7 @@ int tacsl_force_field_noalloc(tacsl_plan plan, const tacsl_state* state, const t
 
 int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* tmpl_bin, const float* scale,
                                float clip) {
+  const Range range("tacsl_plan_set_observation");
   if (!plan) return TACSL_ERR_NULL_ARG;
   if (plan->live_graphs > 0) return TACSL_ERR_STATE;
   if (n_bins == 0) {
@@ -876,6 +892,7 @@ int tacsl_plan_set_observation(tacsl_plan plan, int32_t n_bins, const int32_t* t
 
 int tacsl_force_field_observe(tacsl_plan plan, const tacsl_state* state, const tacsl_outputs* out, float* obs,
                               hipStream_t stream) {
+  const Range range("tacsl_force_field_observe");
   if (!plan) return TACSL_ERR_NULL_ARG;
   if (plan->obs_n == 0) return TACSL_ERR_STATE;
   int rc = check_state(plan, state);
@@ -900,6 +917,7 @@ int tacsl_plan_set_normal_law(tacsl_plan plan, float exponent) {
 }
 
 int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam) {
+  const Range range("tacsl_plan_set_camera");
   if (!plan) return TACSL_ERR_NULL_ARG;
   if (!cam) {
     plan->has_cam = false;
@@ -998,6 +1016,7 @@ int tacsl_plan_set_camera(tacsl_plan plan, const tacsl_camera* cam) {
 
 int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, uint32_t* status,
                       hipStream_t stream) {
+  const Range range("tacsl_depth_image");
   if (!plan) return TACSL_ERR_NULL_ARG;
   if (!plan->has_cam) return TACSL_ERR_STATE;
   int rc = check_state(plan, state);
@@ -1060,6 +1079,7 @@ int tacsl_depth_image(tacsl_plan plan, const tacsl_state* state, float* image, u
 
 int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const tacsl_grads* g,
                                hipStream_t stream) {
+  const Range range("tacsl_force_field_backward");
   if (!plan) return TACSL_ERR_NULL_ARG;
   int rc = check_state(plan, state);
   if (rc != TACSL_OK) return rc;
@@ -1136,6 +1156,7 @@ int tacsl_force_field_backward(tacsl_plan plan, const tacsl_state* state, const 
 
 int tacsl_pose_step(int32_t n_env, const float* pose0, const float* twist, double t, float* pose,
                     hipStream_t stream) {
+  const Range range("tacsl_pose_step");
   if (n_env < 0) return TACSL_ERR_SHAPE;
   if (n_env == 0) return TACSL_OK;
   if (!pose0 || !twist || !pose) return TACSL_ERR_NULL_ARG;
@@ -1150,6 +1171,7 @@ int tacsl_graph_create(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps
 
 int tacsl_graph_create_path(int32_t n_plans, const tacsl_plan* plans, int32_t n_steps, const tacsl_pose_path* paths,
                             const tacsl_state* states, const tacsl_outputs* outs, tacsl_graph* out) {
+  const Range range("tacsl_graph_create_path");
   if (!out) return TACSL_ERR_NULL_ARG;
   *out = nullptr;
   if (!plans || !states || !outs) return TACSL_ERR_NULL_ARG;
@@ -1213,6 +1235,7 @@ int tacsl_graph_create_path(int32_t n_plans, const tacsl_plan* plans, int32_t n_
 }
 
 int tacsl_graph_launch(tacsl_graph graph, hipStream_t stream) {
+  const Range range("tacsl_graph_launch");
   if (!graph || !graph->exec) return TACSL_ERR_NULL_ARG;
   return hipGraphLaunch(graph->exec, stream) == hipSuccess ? TACSL_OK : TACSL_ERR_HIP;
 }

@@ -67,7 +67,7 @@ def test_host_code_under_asan():
                                               "-c", os.path.join(PKG, "csrc", "tacsl_plan.cpp"), "-o", obj])
     # the ASan runtime is not linked in: it is preloaded into the child
     subprocess.check_call([cc, f"--offload-arch={b.ARCH}", "-shared", "-fPIC", "-o", lib, obj] + KERNEL_OBJS +
-                          ["-Wl,-rpath,/opt/rocm/lib", "-L/opt/rocm/lib", "-lamdhip64"])
+                          ["-Wl,-rpath,/opt/rocm/lib", "-L/opt/rocm/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx"])
     nm = shutil.which("nm")
     if nm:
         undef = subprocess.run([nm, "-D", "--undefined-only", lib], capture_output=True, text=True).stdout
